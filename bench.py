@@ -1,0 +1,204 @@
+#!/usr/bin/env python3
+"""Benchmark of the chi0(R, tau) -> E_c path on one MI355X.
+
+A step is one pass of the whole path on device-resident inputs:
+  build_chi0_tau -> chi0_tau_to_omega -> chi0_R_to_q -> rpa_correlation_energy.
+Workload: the 8-atom diamond-like cell (a = 5.4 A, 4x4x4 k-mesh, 26 NAO / 100 ABF per atom,
+16 tau/omega points, 10 A cutoff), seeded synthetic inputs.
+
+Prints one JSON line.  `value` is the algorithmic flop count of the chi0 build (Algorithm 1
+with its N intermediate evaluated once per (V, K, R1-R)) divided by the wall time of the whole
+step, in TFLOP/s.  The same inputs run once through the FP64 path (outside the timed region)
+for the chi0 and E_c errors of the mixed path.  The cpu_baseline leg times the FP64 oracle on
+a bounded sample of the same workload on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--workload", type=int, default=1, help="workload index (1: 8-atom diamond-like cell)")
+    ap.add_argument("--no-fp64-check", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    return ap.parse_args()
+
+
+def cpu_baseline(inp, budget_s):
+    """Time the FP64 oracle (Algorithm 1) on a bounded sample: tau_0, atom V = 0, its N
+    intermediate for every (K, dR), then blocks (U, V=0, R) until the time budget is spent."""
+    from oracle import chi0 as ochi
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([t.get("num_threads", 0) for t in threadpool_info()] + [1])
+    except Exception:
+        threads = os.cpu_count()
+    alg = ochi.Alg1(inp)
+    nao, naux, nR, nb = inp.nao, inp.naux, inp.nR, inp.nb
+    S = [sum(nao[inp.blocks.K[b]] for b in alg.nbrs[a]) for a in range(inp.natoms)]
+    V = 0
+    t0 = time.perf_counter()
+    alg.N_all(0, V)
+    flops = 2.0 * nR * 2.0 * naux[V] * nao[V] * nb * S[V]
+    nblk = 0
+    for U in range(inp.natoms):
+        for R in range(nR):
+            if time.perf_counter() - t0 > budget_s:
+                break
+            alg.block(0, U, V, R)
+            nU, aU, nV, aV = nao[U], naux[U], nao[V], naux[V]
+            flops += 2.0 * 2.0 * nU * aV * nV * S[V] + 8.0 * nU * nV * aV * S[U] + 2.0 * aU * aV * nU * S[U]
+            nblk += 1
+    dt = time.perf_counter() - t0
+    return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": int(threads), "kind": "oracle",
+            "sample": "tau_0, N intermediate of atom 0 for all (K, dR), then %d blocks (U, V=0, R) of "
+                      "Algorithm 1; %.1f s, %.3g algorithmic flops" % (nblk, dt, flops)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: the path is measured on one MI355X "
+              "(multi-GPU sharding is a design note only); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2407_19930_amd import (Context, Plan, build_chi0_tau, chi0_R_to_q, chi0_tau_to_omega,
+                                      rpa_correlation_energy, rpa_ec_workspace_size)
+    from rpa_synth import config, make_inputs
+
+    cell = config(args.workload)
+    t0 = time.perf_counter()
+    inp = make_inputs(cell)
+    log("inputs generated in %.1f s: %s natoms=%d nb=%d naux=%d nR=%d ntau=%d nblk=%d"
+        % (time.perf_counter() - t0, cell.name, inp.natoms, inp.nb, inp.nauxtot, inp.nR, inp.ntau,
+           len(inp.blocks.I)))
+    dev = "cuda"
+    Gocc = torch.from_numpy(inp.Gocc).to(dev)
+    Gun = torch.from_numpy(inp.Gun).to(dev)
+    C = torch.from_numpy(inp.blocks.C).to(dev)
+    vq = torch.from_numpy(inp.vq).to(dev)
+    N, nR, nt, nw, nq = inp.nauxtot, inp.nR, inp.ntau, len(inp.omega), len(inp.kfrac)
+    chi_tau = torch.empty((nt, nR, N, N), dtype=torch.float64, device=dev)
+    chi_w = torch.empty((nw, nR, N, N), dtype=torch.float64, device=dev)
+    chi_q = torch.empty((nw, nq, N, N), dtype=torch.complex128, device=dev)
+    ws_ec = torch.empty(rpa_ec_workspace_size(N, nq, nw), dtype=torch.uint8, device=dev)
+    ctx = Context(0)
+    b = inp.blocks
+
+    def make_plan(prec):
+        p = Plan(ctx, inp.nao, inp.naux, cell.mesh, b.I, b.K, b.R, b.off, nt, prec)
+        return p, torch.empty(max(p.workspace_bytes, 1), dtype=torch.uint8, device=dev)
+
+    def step(plan, ws):
+        build_chi0_tau(plan, inp.spin_factor, Gocc, Gun, C, ws, chi_tau)
+        chi0_tau_to_omega(ctx, inp.gamma_cos, chi_tau, chi_w)
+        chi0_R_to_q(ctx, cell.mesh, inp.kfrac, chi_w, chi_q)
+        return rpa_correlation_energy(ctx, inp.womega, chi_q, vq, ws_ec)
+
+    extra = {}
+    if not args.no_fp64_check and args.precision != "fp64":
+        p64, ws64 = make_plan("fp64")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ec64, _ = step(p64, ws64)
+        torch.cuda.synchronize()
+        t64 = time.perf_counter() - t0
+        chi64 = chi_tau.clone()
+        log("fp64 reference step %.2f s, E_c/atom %.12g" % (t64, ec64 / inp.natoms))
+        del ws64, p64
+        extra["fp64_ms_per_step"] = t64 * 1e3
+    plan, ws = make_plan(args.precision)
+    alg_flops, exec_flops = plan.flops()
+    for i in range(args.warmup):
+        step(plan, ws)
+        log("warmup step %d done" % i)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ec, ecq = step(plan, ws)
+        log("timed step %d done" % i)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    kt = {k: ctx.profile_read(k) for k in ("pack_c", "convert_g", "nstage", "fused", "cos_transform", "r2q",
+                                           "ec_stage")}
+    ctx.profile(False)
+    build_ms = sum(kt[k][0] for k in ("pack_c", "convert_g", "nstage", "fused")) / args.steps
+    ec_ms = sum(kt[k][0] for k in ("cos_transform", "r2q", "ec_stage")) / args.steps
+
+    # dominant kernel and its roofline
+    dom = max(("nstage", "fused"), key=lambda k: kt[k][0])
+    stage = 0 if dom == "nstage" else 1
+    st_alg, st_exec = plan.stage_flops(stage)
+    per_launch = st_alg / nt
+    avg_ms = kt[dom][0] / max(kt[dom][1], 1)
+    achieved = per_launch / (avg_ms * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[args.precision]
+    roofline = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                "traffic": None, "kernel": dom,
+                "executed_tflops": st_exec / nt / (avg_ms * 1e-3) / 1e12}
+
+    if not args.no_fp64_check and args.precision != "fp64":
+        d = chi_tau - chi64
+        extra["chi_rel_err_vs_fp64"] = float(torch.linalg.vector_norm(d) / torch.linalg.vector_norm(chi64))
+        extra["dEc_per_atom_vs_fp64"] = abs(ec - ec64) / inp.natoms
+        extra["speedup_vs_fp64"] = extra["fp64_ms_per_step"] / (dt * 1e3)
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(inp, args.cpu_seconds)
+        log("cpu baseline: %s" % cpu)
+
+    rec = {
+        "metric": "chi0(R,tau) build TFLOP/s + E_c time, mixed vs FP64 at |dE_c| <= 1e-6 Ha/atom",
+        "value": alg_flops / dt / 1e12,
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.precision,
+        "data": "synthetic",
+        "config": {"workload": "%s: %d atoms, %d NAO / %d ABF per cell, %dx%dx%d k-mesh, %d tau, rcut %.0f A"
+                   % (cell.name, inp.natoms, inp.nb, N, *cell.mesh, nt, cell.rcut),
+                   "natoms": inp.natoms, "nao_total": inp.nb, "naux_total": N, "mesh": list(cell.mesh),
+                   "ntau": nt, "rcut": cell.rcut, "lri_blocks": int(len(b.I))},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "alg_tflop_per_step": alg_flops / 1e12,
+        "exec_tflop_per_step": exec_flops / 1e12,
+        "build_ms": build_ms,
+        "build_tflops": alg_flops / (build_ms * 1e-3) / 1e12,
+        "ec_time_ms": ec_ms,
+        "kernel_ms": {k: v[0] / args.steps for k, v in kt.items()},
+        "Ec_per_atom": ec / inp.natoms,
+    }
+    rec.update(extra)
+    print(json.dumps(rec))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,181 @@
+/*
+ * rpa_mi355x.h - C ABI of the MI355X (gfx950) library for the space-time
+ * chi0 -> RPA correlation energy path of the LRI/NAO low-scaling RPA method
+ * (arXiv 2407.19930, Sec. 2 and Algorithm 1).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Plain pointers and sizes only.  "device" arrays live in GPU memory owned
+ *   by the caller (for instance torch tensors' data_ptr()); "host" arrays live
+ *   in CPU memory owned by the caller.  The library never frees or keeps a
+ *   caller pointer beyond the call.
+ * - Row-major, contiguous.  Complex numbers are interleaved (re, im) FP64.
+ * - All device work of a call is queued on the context's HIP stream and is
+ *   asynchronous with respect to the host, except where a call returns host
+ *   values (rpa_correlation_energy), which synchronises the stream.
+ * - Real-valued convention for tau > 0 (Sec. 2, Eq. (green_mat)): the paper's
+ *   G(R, i tau) = i G^un(R, tau) and G(R, -i tau) = -i G^occ(R, tau) with
+ *   G^occ, G^un real; the paper's chi0(R, i tau) = i chi(R, tau) with chi real.
+ *   The inputs must satisfy G^s(-R) = G^s(R)^T (real Hermitian Green's
+ *   functions, time-reversal symmetric); the kernels rely on it.
+ * - BvK supercell: lattice vectors R are integer triples n in
+ *   [0,N1)x[0,N2)x[0,N3) flattened as (n1*N2 + n2)*N3 + n3; the k/q mesh
+ *   (Gamma-centred, k = n/N) uses the same ordering.
+ * - Return value: RPA_OK (0) or an rpa_status error code; nothing is thrown
+ *   across the ABI.  rpa_last_error() returns a message for the last failing
+ *   call on a context.  On error, output arrays are unspecified and inputs are
+ *   unchanged (inputs are never written).
+ */
+#ifndef RPA_MI355X_H
+#define RPA_MI355X_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__)
+#define RPA_API __attribute__((visibility("default")))
+#else
+#define RPA_API
+#endif
+
+typedef enum {
+  RPA_OK = 0,
+  RPA_ERR_ARG = 1,          /* null pointer, bad enum, negative size */
+  RPA_ERR_SHAPE = 2,        /* inconsistent sizes (atoms, blocks, mesh, tau) */
+  RPA_ERR_WORKSPACE = 3,    /* workspace smaller than the queried size */
+  RPA_ERR_NOT_HPD = 4,      /* a matrix to be Cholesky-factorised is not Hermitian positive definite */
+  RPA_ERR_NONFINITE = 5,    /* NaN or Inf met in a reduction */
+  RPA_ERR_HIP = 6,          /* HIP runtime error */
+  RPA_ERR_UNSUPPORTED = 7   /* shape outside the compiled kernel limits */
+} rpa_status;
+
+typedef enum {
+  RPA_FP64 = 0,             /* every contraction in FP64 (MFMA f64) */
+  RPA_FP32 = 1              /* contractions in FP32 (MFMA f32), FP64 across neighbour blocks */
+} rpa_precision;
+
+typedef struct rpa_ctx rpa_ctx;
+typedef struct rpa_plan rpa_plan;
+
+/* One periodic cell: atoms with their NAO / ABF counts and the k-mesh (= BvK
+ * supercell).  Limits of this build: nao[a] <= 32, naux[a] <= 128. */
+typedef struct {
+  int natoms;
+  const int *nao;           /* host [natoms] */
+  const int *naux;          /* host [natoms] */
+  int mesh[3];              /* N1, N2, N3 >= 1 */
+} rpa_cell;
+
+/* LRI triple coefficients (Sec. 2, Eq. (eq:LRI)): one block per ordered
+ * neighbour pair (I, K(R)) with the ABF index on I, stored as
+ * C[off[b] + (mu * nao[I] + i) * nao[K] + k] = C^{mu(0)}_{i(0), k(R)}.
+ * The set of blocks with first atom U is the neighbourhood N[U] of
+ * Algorithm 1.  Blocks are read, never written; their order is free. */
+typedef struct {
+  int nblk;
+  const int *I;             /* host [nblk] */
+  const int *K;             /* host [nblk] */
+  const int *R;             /* host [3*nblk], unfolded integer lattice vector of K */
+  const long long *off;     /* host [nblk], element offset of the block in C */
+} rpa_lri_blocks;
+
+/* Create / destroy a context bound to one device and one HIP stream
+ * (hip_stream may be NULL for the default stream; pass torch's current stream
+ * to order the library's work with torch's). */
+RPA_API int rpa_create(rpa_ctx **ctx, int device, void *hip_stream);
+RPA_API int rpa_set_stream(rpa_ctx *ctx, void *hip_stream);
+RPA_API void rpa_destroy(rpa_ctx *ctx);
+RPA_API const char *rpa_last_error(const rpa_ctx *ctx);
+
+/* Plan for one cell: neighbour tables, BvK fold tables and work lists of
+ * Algorithm 1 (atom pairs U <= V, Sec. 3.2; lattice vectors R; tau points).
+ * The plan owns small device tables; *workspace_bytes receives the size of the
+ * caller-owned device workspace every compute call of this plan needs.  A plan
+ * must be destroyed before its context; rpa_plan_destroy waits for the device.
+ * Errors: RPA_ERR_ARG, RPA_ERR_SHAPE, RPA_ERR_UNSUPPORTED, RPA_ERR_HIP. */
+RPA_API int rpa_plan_create(rpa_ctx *ctx, const rpa_cell *cell, const rpa_lri_blocks *blocks,
+                    int ntau, int precision, size_t *workspace_bytes, rpa_plan **plan);
+RPA_API int rpa_plan_destroy(rpa_plan *plan);
+
+/* Algorithmic flop count of the chi0 build for this plan (Algorithm 1 with
+ * its N intermediate evaluated once per (V, K, R1-R)), and the flops the
+ * kernels actually execute (padding excluded). Host values. */
+RPA_API int rpa_plan_flops(const rpa_plan *plan, double *alg_flops, double *exec_flops);
+
+/* Per-kernel split of the same counts: stage 0 = N-stage kernel (the N intermediate
+ * of Algorithm 1), stage 1 = fused kernel (X, M, Z, O and chi += C O of Algorithm 1).
+ * Errors: RPA_ERR_ARG. */
+RPA_API int rpa_plan_stage_flops(const rpa_plan *plan, int stage, double *alg_flops, double *exec_flops);
+
+/* Opt-in kernel timing with HIP events recorded on the context's stream around
+ * every launch of the library's kernels.  rpa_profile(ctx, 1) enables and resets,
+ * rpa_profile(ctx, 0) disables.  rpa_profile_read waits for the recorded events and
+ * returns the summed duration and launch count of one kernel ("pack_c", "convert_g",
+ * "nstage", "fused", "cos_transform", "r2q", "ec_stage").  Errors: RPA_ERR_ARG, RPA_ERR_HIP. */
+RPA_API int rpa_profile(rpa_ctx *ctx, int enable);
+RPA_API int rpa_profile_read(rpa_ctx *ctx, const char *kernel, double *total_ms, int *launches);
+
+/* chi(R, tau) of Algorithm 1 for every atom pair and lattice vector
+ * (Sec. 2, the chi0_{mu,nu}(R, i tau) formula; Algorithm 1):
+ *   chi_{mu nu}(R, tau) = -s sum_{K(R1) in N[U]} sum_{i k} C^mu_{ik}(R1) O^nu_{ik}(R1, R, tau) + ...
+ * with s = spin_factor (2 for closed shells).
+ *   G_occ, G_un : device FP64 [ntau][nR][nb][nb]  (nb = sum of nao)
+ *   C           : device FP64, blocks as described by rpa_lri_blocks
+ *   workspace   : device, at least the size returned by rpa_plan_create
+ *   chi0_tau    : device FP64 [ntau][nR][naux_tot][naux_tot], written in full
+ * Errors: RPA_ERR_ARG, RPA_ERR_WORKSPACE, RPA_ERR_HIP. */
+RPA_API int build_chi0_tau(rpa_plan *plan, double spin_factor, const double *G_occ, const double *G_un,
+                   const double *C, void *workspace, size_t workspace_bytes, double *chi0_tau);
+
+/* Cosine transform tau -> i omega (Sec. 2, the chi0(R, i omega_k) equation):
+ *   chi(R, i omega_k) = sum_j Gamma_kj chi(R, tau_j),  Gamma_kj = gamma_jk cos(tau_j omega_k)
+ * (the paper's -i and chi0 = i chi cancel).
+ *   gamma_cos  : host FP64 [nomega][ntau]
+ *   chi0_tau   : device FP64 [ntau][n]   chi0_omega : device FP64 [nomega][n]
+ *   n          : elements per time point (nR * naux_tot^2 for a plan's chi)
+ * Errors: RPA_ERR_ARG, RPA_ERR_HIP. */
+RPA_API int chi0_tau_to_omega(rpa_ctx *ctx, int ntau, int nomega, size_t n, const double *gamma_cos,
+                      const double *chi0_tau, double *chi0_omega);
+
+/* Fourier transform R -> q (Sec. 2, the chi0(q, i omega) equation):
+ *   chi(q) = sum_R exp(2 pi i q_frac . n_R) chi(R)
+ *   mesh        : BvK mesh of the R axis (nR = N1 N2 N3)
+ *   q_frac      : host FP64 [nq][3] fractional reciprocal coordinates
+ *   chi0_R      : device FP64 [nbatch][nR][m]
+ *   chi0_q      : device complex128 interleaved [nbatch][nq][m]
+ * Errors: RPA_ERR_ARG, RPA_ERR_HIP. */
+RPA_API int chi0_R_to_q(rpa_ctx *ctx, const int mesh[3], int nbatch, size_t m, int nq, const double *q_frac,
+                const double *chi0_R, double *chi0_q);
+
+/* Correlation energy (Sec. 2, the E_c^RPA equations with Tr ln = ln det):
+ *   E_c = 1/(2 pi) 1/nq sum_q sum_k w_k { ln det[1 - chi(q, i w_k) v(q)] + Tr[chi v] }
+ * evaluated as ln det(I - B) + Tr B with B = L^H chi L, v(q) = L L^H (Cholesky,
+ * FP64), det(1 - chi L L^H) = det(I - L^H chi L); I - B is Hermitian positive
+ * definite when chi is negative semidefinite, and its log-determinant is
+ * twice the sum of the logs of its Cholesky diagonal.
+ *   n           : matrix order (naux_tot)
+ *   womega      : host FP64 [nomega]
+ *   chi0_q      : device complex128 [nomega][nq][n][n]
+ *   v_q         : device complex128 [nq][n][n], Hermitian positive definite
+ *   workspace   : device; rpa_ec_workspace_size(n, nq, nomega) bytes run every
+ *                 frequency of a q at once, less (down to the size the same
+ *                 formula gives with one frequency per batch) processes the
+ *                 frequencies in smaller batches
+ *   Ec          : host, E_c per cell (Hartree)
+ *   Ec_q        : host [nq] per-q contributions (already divided by nq), or NULL
+ * Synchronises the stream.  Errors: RPA_ERR_ARG, RPA_ERR_WORKSPACE,
+ * RPA_ERR_NOT_HPD (v(q) or I - B not HPD; the message names q and omega index),
+ * RPA_ERR_NONFINITE, RPA_ERR_HIP. */
+RPA_API size_t rpa_ec_workspace_size(int n, int nq, int nomega);
+RPA_API int rpa_correlation_energy(rpa_ctx *ctx, int n, int nq, int nomega, const double *womega,
+                           const double *chi0_q, const double *v_q, void *workspace,
+                           size_t workspace_bytes, double *Ec, double *Ec_q);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RPA_MI355X_H */

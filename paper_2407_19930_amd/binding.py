@@ -1,0 +1,257 @@
+"""Thin ctypes binding of librpa_mi355x.so (include/rpa_mi355x.h).
+
+Argument marshalling only: every step of the path runs in the HIP library.
+torch tensors provide device memory and the HIP stream; host arrays are numpy.
+Importing this module fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import weakref
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librpa_mi355x.so")
+
+RPA_OK, RPA_ERR_ARG, RPA_ERR_SHAPE, RPA_ERR_WORKSPACE, RPA_ERR_NOT_HPD, RPA_ERR_NONFINITE, RPA_ERR_HIP, \
+    RPA_ERR_UNSUPPORTED = range(8)
+RPA_FP64, RPA_FP32 = 0, 1
+PRECISIONS = {"fp64": RPA_FP64, "fp32": RPA_FP32}
+
+EXPORTED = ["rpa_create", "rpa_set_stream", "rpa_destroy", "rpa_last_error", "rpa_plan_create",
+            "rpa_plan_destroy", "rpa_plan_flops", "rpa_plan_stage_flops", "rpa_profile", "rpa_profile_read",
+            "build_chi0_tau", "chi0_tau_to_omega", "chi0_R_to_q", "rpa_ec_workspace_size",
+            "rpa_correlation_energy"]
+
+
+class RpaError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("rpa error %d: %s" % (code, msg))
+        self.code = code
+
+
+class _Cell(ctypes.Structure):
+    _fields_ = [("natoms", ctypes.c_int), ("nao", ctypes.POINTER(ctypes.c_int)),
+                ("naux", ctypes.POINTER(ctypes.c_int)), ("mesh", ctypes.c_int * 3)]
+
+
+class _Blocks(ctypes.Structure):
+    _fields_ = [("nblk", ctypes.c_int), ("I", ctypes.POINTER(ctypes.c_int)), ("K", ctypes.POINTER(ctypes.c_int)),
+                ("R", ctypes.POINTER(ctypes.c_int)), ("off", ctypes.POINTER(ctypes.c_longlong))]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load the library (once).  Raises ImportError if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError("librpa_mi355x.so not built (run __graft_entry__.build() or "
+                          "python paper_2407_19930_amd/build.py)")
+    lib = ctypes.CDLL(path)
+    vp, i, sz, dp = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t, ctypes.c_double
+    lib.rpa_create.argtypes = [ctypes.POINTER(vp), i, vp]
+    lib.rpa_set_stream.argtypes = [vp, vp]
+    lib.rpa_destroy.argtypes = [vp]
+    lib.rpa_destroy.restype = None
+    lib.rpa_last_error.argtypes = [vp]
+    lib.rpa_last_error.restype = ctypes.c_char_p
+    lib.rpa_plan_create.argtypes = [vp, ctypes.POINTER(_Cell), ctypes.POINTER(_Blocks), i, i,
+                                    ctypes.POINTER(sz), ctypes.POINTER(vp)]
+    lib.rpa_plan_destroy.argtypes = [vp]
+    lib.rpa_plan_flops.argtypes = [vp, ctypes.POINTER(dp), ctypes.POINTER(dp)]
+    lib.rpa_plan_stage_flops.argtypes = [vp, i, ctypes.POINTER(dp), ctypes.POINTER(dp)]
+    lib.rpa_profile.argtypes = [vp, i]
+    lib.rpa_profile_read.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(dp), ctypes.POINTER(i)]
+    lib.build_chi0_tau.argtypes = [vp, dp, vp, vp, vp, vp, sz, vp]
+    lib.chi0_tau_to_omega.argtypes = [vp, i, i, sz, vp, vp, vp]
+    lib.chi0_R_to_q.argtypes = [vp, ctypes.POINTER(ctypes.c_int), i, sz, i, vp, vp, vp]
+    lib.rpa_ec_workspace_size.argtypes = [i, i, i]
+    lib.rpa_ec_workspace_size.restype = sz
+    lib.rpa_correlation_energy.argtypes = [vp, i, i, i, vp, vp, vp, vp, sz, ctypes.POINTER(dp), vp]
+    for name in EXPORTED:
+        if name not in ("rpa_destroy", "rpa_last_error", "rpa_ec_workspace_size"):
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _dev(t, dtype=None):
+    """Device pointer of a contiguous torch tensor (checked)."""
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a device torch tensor")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError("expected %s, got %s" % (dtype, t.dtype))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _host(a, dtype):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, a.ctypes.data_as(ctypes.c_void_p)
+
+
+class Context:
+    """rpa_create / rpa_destroy.  Binds torch's current stream of `device` unless one is given."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self.lib = load()
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        rc = self.lib.rpa_create(ctypes.byref(h), device, ctypes.c_void_p(stream.cuda_stream))
+        if rc != RPA_OK:
+            raise RpaError(rc, "rpa_create failed")
+        self.h = h
+        self._plans = weakref.WeakSet()
+
+    def check(self, rc):
+        if rc != RPA_OK:
+            raise RpaError(rc, self.lib.rpa_last_error(self.h).decode())
+
+    def profile(self, enable: bool):
+        """rpa_profile: HIP-event timing of every library kernel launch (resets totals)."""
+        self.check(self.lib.rpa_profile(self.h, 1 if enable else 0))
+
+    def profile_read(self, kernel: str):
+        """rpa_profile_read: (total milliseconds, launches) of one kernel."""
+        ms, n = ctypes.c_double(), ctypes.c_int()
+        self.check(self.lib.rpa_profile_read(self.h, kernel.encode(), ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            for p in list(getattr(self, "_plans", ())):
+                p.close()               # plans hold a pointer to the context
+            self.lib.rpa_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Plan:
+    """rpa_plan_create for one cell.  Arguments mirror rpa_cell and rpa_lri_blocks."""
+
+    def __init__(self, ctx: Context, nao, naux, mesh, blk_I, blk_K, blk_R, blk_off, ntau: int,
+                 precision: str = "fp64"):
+        self.ctx = ctx
+        self._keep = []
+        nao_a, nao_p = _host(nao, np.int32)
+        naux_a, naux_p = _host(naux, np.int32)
+        cell = _Cell(len(nao_a), ctypes.cast(nao_p, ctypes.POINTER(ctypes.c_int)),
+                     ctypes.cast(naux_p, ctypes.POINTER(ctypes.c_int)), (ctypes.c_int * 3)(*[int(x) for x in mesh]))
+        I_a, I_p = _host(blk_I, np.int32)
+        K_a, K_p = _host(blk_K, np.int32)
+        R_a, R_p = _host(np.asarray(blk_R).reshape(-1), np.int32)
+        o_a, o_p = _host(blk_off, np.int64)
+        blocks = _Blocks(len(I_a), ctypes.cast(I_p, ctypes.POINTER(ctypes.c_int)),
+                         ctypes.cast(K_p, ctypes.POINTER(ctypes.c_int)), ctypes.cast(R_p, ctypes.POINTER(ctypes.c_int)),
+                         ctypes.cast(o_p, ctypes.POINTER(ctypes.c_longlong)))
+        ws = ctypes.c_size_t()
+        h = ctypes.c_void_p()
+        ctx.check(ctx.lib.rpa_plan_create(ctx.h, ctypes.byref(cell), ctypes.byref(blocks), int(ntau),
+                                          PRECISIONS[precision], ctypes.byref(ws), ctypes.byref(h)))
+        self.h = h
+        ctx._plans.add(self)
+        self.workspace_bytes = ws.value
+        self.ntau = int(ntau)
+        self.precision = precision
+        self.nauxtot = int(np.sum(naux_a))
+        self.nR = int(np.prod(mesh))
+
+    def flops(self):
+        """rpa_plan_flops: (algorithmic, executed) flops of the whole chi0 build."""
+        a, e = ctypes.c_double(), ctypes.c_double()
+        self.ctx.check(self.ctx.lib.rpa_plan_flops(self.h, ctypes.byref(a), ctypes.byref(e)))
+        return a.value, e.value
+
+    def stage_flops(self, stage: int):
+        """rpa_plan_stage_flops: stage 0 = N-stage kernel, 1 = fused kernel."""
+        a, e = ctypes.c_double(), ctypes.c_double()
+        self.ctx.check(self.ctx.lib.rpa_plan_stage_flops(self.h, int(stage), ctypes.byref(a), ctypes.byref(e)))
+        return a.value, e.value
+
+    def close(self):
+        if getattr(self, "h", None) and getattr(self.ctx, "h", None):
+            self.ctx.lib.rpa_plan_destroy(self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def build_chi0_tau(plan: Plan, spin_factor: float, G_occ, G_un, C, workspace, chi0_tau):
+    import torch
+    f64 = torch.float64
+    ctx = plan.ctx
+    ctx.check(ctx.lib.build_chi0_tau(plan.h, float(spin_factor), _dev(G_occ, f64), _dev(G_un, f64),
+                                     _dev(C, f64), _dev(workspace), workspace.numel() * workspace.element_size(),
+                                     _dev(chi0_tau, f64)))
+
+
+def chi0_tau_to_omega(ctx: Context, gamma_cos, chi0_tau, chi0_omega):
+    import torch
+    g, gp = _host(gamma_cos, np.float64)
+    nomega, ntau = g.shape
+    n = chi0_tau.numel() // ntau
+    if chi0_tau.numel() != n * ntau or chi0_omega.numel() != n * nomega:
+        raise ValueError("shape mismatch")
+    ctx.check(ctx.lib.chi0_tau_to_omega(ctx.h, ntau, nomega, n, gp, _dev(chi0_tau, torch.float64),
+                                        _dev(chi0_omega, torch.float64)))
+
+
+def chi0_R_to_q(ctx: Context, mesh, q_frac, chi0_R, chi0_q):
+    """chi0_R: [nbatch, nR, ...] float64; chi0_q: [nbatch, nq, ..., 2] float64 (re, im) or complex128."""
+    import torch
+    q, qp = _host(q_frac, np.float64)
+    nq = q.shape[0]
+    nR = int(np.prod(mesh))
+    nbatch = chi0_R.shape[0]
+    m = chi0_R.numel() // (nbatch * nR)
+    if chi0_R.numel() != nbatch * nR * m:
+        raise ValueError("shape mismatch")
+    out = chi0_q
+    if out.dtype == torch.complex128:
+        out = torch.view_as_real(out)
+    if out.numel() != nbatch * nq * m * 2:
+        raise ValueError("output shape mismatch")
+    mesh_a = (ctypes.c_int * 3)(*[int(x) for x in mesh])
+    ctx.check(ctx.lib.chi0_R_to_q(ctx.h, mesh_a, nbatch, m, nq, qp, _dev(chi0_R, torch.float64), _dev(out)))
+
+
+def rpa_ec_workspace_size(n: int, nq: int, nomega: int) -> int:
+    return int(load().rpa_ec_workspace_size(int(n), int(nq), int(nomega)))
+
+
+def rpa_correlation_energy(ctx: Context, womega, chi0_q, v_q, workspace):
+    """Returns (E_c per cell, per-q contributions).  chi0_q [nomega, nq, n, n] and v_q [nq, n, n]
+    complex128 (or float64 with a trailing (re, im) axis)."""
+    import torch
+    w, wp = _host(womega, np.float64)
+    cq = torch.view_as_real(chi0_q) if chi0_q.dtype == torch.complex128 else chi0_q
+    vq = torch.view_as_real(v_q) if v_q.dtype == torch.complex128 else v_q
+    nomega, nq, n = chi0_q.shape[0], chi0_q.shape[1], chi0_q.shape[2]
+    ec = ctypes.c_double()
+    ecq = np.zeros(nq)
+    ctx.check(ctx.lib.rpa_correlation_energy(ctx.h, n, nq, nomega, wp, _dev(cq, torch.float64),
+                                             _dev(vq, torch.float64), _dev(workspace),
+                                             workspace.numel() * workspace.element_size(), ctypes.byref(ec),
+                                             ecq.ctypes.data_as(ctypes.c_void_p)))
+    return ec.value, ecq

@@ -1,0 +1,679 @@
+// C ABI of the chi0 -> E_c library (declared in include/rpa_mi355x.h): contexts,
+// plans (neighbour tables and work lists of Algorithm 1) and the four compute calls.
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <memory>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/rpa_mi355x.h"
+#include "chi0_kernels.h"
+#include "ec_kernels.h"
+
+hipError_t launch_cos_transform(const double *W_dev, int ntau, int nomega, size_t n, const double *x, double *y,
+                                hipStream_t s);
+hipError_t launch_r2q(const double *ph_dev, int nR, int nq, int nbatch, size_t m, const double *x, double *y,
+                      hipStream_t s);
+
+struct rpa_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  double *params = nullptr;        // small device buffer for per-call weights and phases
+  size_t params_bytes = 0;
+  std::string err;
+  // opt-in kernel timing
+  bool profile = false;
+  struct Pending {
+    std::string name;
+    hipEvent_t a, b;
+  };
+  std::vector<Pending> pending;
+  std::map<std::string, std::pair<double, int>> totals;
+};
+
+namespace {
+
+constexpr size_t kParamsBytes = 1 << 20;
+
+int fail(rpa_ctx *ctx, int code, const std::string &msg) {
+  if (ctx) ctx->err = msg;
+  return code;
+}
+
+#define HIP_TRY(ctx, expr)                                                                   \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
+      return fail((ctx), RPA_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));    \
+  } while (0)
+
+size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+// Records HIP events around the enclosed launches when profiling is on.
+struct Timed {
+  rpa_ctx *ctx;
+  const char *name;
+  hipEvent_t a = nullptr, b = nullptr;
+  Timed(rpa_ctx *c, const char *n) : ctx(c), name(n) {
+    if (ctx->profile && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess)
+      hipEventRecord(a, ctx->stream);
+  }
+  ~Timed() {
+    if (a && b) {
+      hipEventRecord(b, ctx->stream);
+      ctx->pending.push_back({name, a, b});
+    }
+  }
+};
+
+int drain_profile(rpa_ctx *ctx) {
+  for (auto &p : ctx->pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(p.b) != hipSuccess || hipEventElapsedTime(&ms, p.a, p.b) != hipSuccess) return RPA_ERR_HIP;
+    auto &t = ctx->totals[p.name];
+    t.first += ms;
+    t.second += 1;
+    hipEventDestroy(p.a);
+    hipEventDestroy(p.b);
+  }
+  ctx->pending.clear();
+  return RPA_OK;
+}
+
+}  // namespace
+
+struct rpa_plan {
+  rpa_ctx *ctx = nullptr;      // must outlive the plan
+  int device = 0;
+  int natoms = 0, nb = 0, nauxtot = 0, nR = 0, ntau = 0, prec = 0, nblk = 0;
+  int mesh[3] = {1, 1, 1};
+  Bvk bvk{1, 1, 1};
+  std::vector<int> nao, naux, ao_off, aux_off, atom_of_ao;
+  std::vector<long long> in_off, out_off;      // caller block offsets, packed offsets
+  std::vector<int> blk_a, blk_ni, blk_nk;
+  long long cp_elems = 0, maxblk = 0;
+  std::vector<int> nbr_start, nbr_K, nbr_R1;
+  std::vector<long long> nbr_cp;
+  std::vector<int> rows_start, row_g, row_dl;
+  std::vector<long long> row_cp;
+  std::vector<long long> noff;
+  long long n_elems = 0;                        // N buffer elements per tau
+  std::vector<int> tileV, tileM, tileN;
+  std::vector<int> itemU, itemV, itemR;
+  double alg_flops = 0, exec_flops = 0;
+  double stage_alg[2] = {0, 0}, stage_exec[2] = {0, 0};
+  // device tables (one allocation owned by the plan)
+  void *dtab = nullptr;
+  Chi0Tables tb{};
+  NTiles tiles{};
+  PairItems items{};
+  PackTables pack{};
+  // workspace layout (bytes)
+  size_t ws_cp = 0, ws_g = 0, ws_n = 0, ws_total = 0;
+};
+
+// ---- correlation energy ----
+namespace {
+struct EcLayout {
+  size_t L, T, B, W, trB, f, flags, ecq, w, total;
+  int cw;
+};
+EcLayout ec_layout(int n, int nq, int nomega, int cw) {
+  EcLayout l{};
+  const size_t mat = (size_t)n * n * 16;
+  size_t o = 0;
+  l.L = o;
+  o = align_up(o + mat);
+  l.T = o;
+  o = align_up(o + mat * cw);
+  l.B = o;
+  o = align_up(o + mat * cw);
+  l.W = o;
+  o = align_up(o + (size_t)std::max(cw, 1) * kCholBlock * kCholBlock * 16);
+  l.trB = o;
+  o = align_up(o + (size_t)nq * nomega * 8);
+  l.f = o;
+  o = align_up(o + (size_t)nq * nomega * 8);
+  l.flags = o;
+  o = align_up(o + (size_t)(nq + nq * nomega) * 4);
+  l.ecq = o;
+  o = align_up(o + (size_t)(nq + 1) * 8);
+  l.w = o;
+  o = align_up(o + (size_t)nomega * 8);
+  l.total = o;
+  l.cw = cw;
+  return l;
+}
+}  // namespace
+
+extern "C" {
+
+int rpa_create(rpa_ctx **out, int device, void *hip_stream) {
+  if (!out) return RPA_ERR_ARG;
+  *out = nullptr;
+  rpa_ctx *ctx = new rpa_ctx();
+  ctx->device = device;
+  ctx->stream = (hipStream_t)hip_stream;
+  hipError_t e = hipSetDevice(device);
+  if (e == hipSuccess) e = hipMalloc(&ctx->params, kParamsBytes);
+  if (e != hipSuccess) {
+    delete ctx;
+    return RPA_ERR_HIP;
+  }
+  ctx->params_bytes = kParamsBytes;
+  *out = ctx;
+  return RPA_OK;
+}
+
+int rpa_set_stream(rpa_ctx *ctx, void *hip_stream) {
+  if (!ctx) return RPA_ERR_ARG;
+  ctx->stream = (hipStream_t)hip_stream;
+  return RPA_OK;
+}
+
+void rpa_destroy(rpa_ctx *ctx) {
+  if (!ctx) return;
+  drain_profile(ctx);
+  if (ctx->params) {
+    hipStreamSynchronize(ctx->stream);
+    hipFree(ctx->params);
+  }
+  delete ctx;
+}
+
+const char *rpa_last_error(const rpa_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int rpa_plan_create(rpa_ctx *ctx, const rpa_cell *cell, const rpa_lri_blocks *blocks, int ntau, int precision,
+                    size_t *workspace_bytes, rpa_plan **out) {
+  if (!ctx) return RPA_ERR_ARG;
+  if (!cell || !blocks || !workspace_bytes || !out) return fail(ctx, RPA_ERR_ARG, "null argument");
+  *out = nullptr;
+  if (cell->natoms <= 0 || !cell->nao || !cell->naux) return fail(ctx, RPA_ERR_ARG, "bad cell");
+  if (ntau <= 0) return fail(ctx, RPA_ERR_ARG, "ntau must be positive");
+  if (precision != RPA_FP64 && precision != RPA_FP32) return fail(ctx, RPA_ERR_ARG, "unknown precision");
+  for (int d = 0; d < 3; ++d)
+    if (cell->mesh[d] <= 0) return fail(ctx, RPA_ERR_ARG, "mesh must be positive");
+  if (blocks->nblk < 0 || (blocks->nblk > 0 && (!blocks->I || !blocks->K || !blocks->R || !blocks->off)))
+    return fail(ctx, RPA_ERR_ARG, "bad block list");
+
+  rpa_plan *p = new rpa_plan();
+  p->ctx = ctx;
+  p->device = ctx->device;
+  p->natoms = cell->natoms;
+  p->ntau = ntau;
+  p->prec = precision;
+  for (int d = 0; d < 3; ++d) p->mesh[d] = cell->mesh[d];
+  p->bvk = Bvk{cell->mesh[0], cell->mesh[1], cell->mesh[2]};
+  p->nR = cell->mesh[0] * cell->mesh[1] * cell->mesh[2];
+  const int na = p->natoms;
+  p->nao.assign(cell->nao, cell->nao + na);
+  p->naux.assign(cell->naux, cell->naux + na);
+  for (int a = 0; a < na; ++a) {
+    if (p->nao[a] <= 0 || p->naux[a] <= 0) {
+      delete p;
+      return fail(ctx, RPA_ERR_SHAPE, "nao and naux must be positive");
+    }
+    if (p->nao[a] > kMaxNao || p->naux[a] > kMaxNaux) {
+      delete p;
+      return fail(ctx, RPA_ERR_UNSUPPORTED, "nao <= 32 and naux <= 128 per atom in this build");
+    }
+  }
+  p->ao_off.resize(na);
+  p->aux_off.resize(na);
+  for (int a = 0, o = 0, x = 0; a < na; ++a) {
+    p->ao_off[a] = o;
+    p->aux_off[a] = x;
+    o += p->nao[a];
+    x += p->naux[a];
+  }
+  p->nb = p->ao_off[na - 1] + p->nao[na - 1];
+  p->nauxtot = p->aux_off[na - 1] + p->naux[na - 1];
+  p->atom_of_ao.resize(p->nb);
+  for (int a = 0; a < na; ++a)
+    for (int i = 0; i < p->nao[a]; ++i) p->atom_of_ao[p->ao_off[a] + i] = a;
+
+  // blocks: validate, packed offsets (caller order), CSR by first atom (stable)
+  const int nblk = blocks->nblk;
+  p->nblk = nblk;
+  p->in_off.resize(nblk);
+  p->out_off.resize(nblk);
+  p->blk_a.resize(nblk);
+  p->blk_ni.resize(nblk);
+  p->blk_nk.resize(nblk);
+  std::vector<int> fR(nblk);
+  long long acc = 0;
+  for (int b = 0; b < nblk; ++b) {
+    const int I = blocks->I[b], K = blocks->K[b];
+    if (I < 0 || I >= na || K < 0 || K >= na || blocks->off[b] < 0) {
+      delete p;
+      return fail(ctx, RPA_ERR_SHAPE, "block atom index or offset out of range");
+    }
+    int f[3];
+    for (int d = 0; d < 3; ++d) {
+      const int m = cell->mesh[d];
+      f[d] = ((blocks->R[3 * b + d] % m) + m) % m;
+    }
+    fR[b] = p->bvk.join(f[0], f[1], f[2]);
+    p->in_off[b] = blocks->off[b];
+    p->out_off[b] = acc;
+    p->blk_a[b] = p->naux[I];
+    p->blk_ni[b] = p->nao[I];
+    p->blk_nk[b] = p->nao[K];
+    const long long sz = (long long)p->naux[I] * p->nao[I] * p->nao[K];
+    p->maxblk = std::max(p->maxblk, sz);
+    acc += sz;
+  }
+  p->cp_elems = acc;
+  p->nbr_start.assign(na + 1, 0);
+  for (int b = 0; b < nblk; ++b) p->nbr_start[blocks->I[b] + 1]++;
+  for (int a = 0; a < na; ++a) p->nbr_start[a + 1] += p->nbr_start[a];
+  std::vector<int> order(nblk), fill(p->nbr_start.begin(), p->nbr_start.end() - 1);
+  for (int b = 0; b < nblk; ++b) order[fill[blocks->I[b]]++] = b;
+  p->nbr_K.resize(nblk);
+  p->nbr_R1.resize(nblk);
+  p->nbr_cp.resize(nblk);
+  for (int e = 0; e < nblk; ++e) {
+    const int b = order[e];
+    p->nbr_K[e] = blocks->K[b];
+    p->nbr_R1[e] = fR[b];
+    p->nbr_cp[e] = p->out_off[b];
+  }
+  // N-stage contraction rows per atom V
+  std::vector<long long> S(na, 0);
+  p->rows_start.assign(na + 1, 0);
+  for (int V = 0; V < na; ++V) {
+    for (int e = p->nbr_start[V]; e < p->nbr_start[V + 1]; ++e) {
+      const int L = p->nbr_K[e];
+      S[V] += p->nao[L];
+      for (int l = 0; l < p->nao[L]; ++l) {
+        p->row_g.push_back(p->ao_off[L] + l);
+        p->row_dl.push_back(p->nbr_R1[e]);
+        p->row_cp.push_back(p->nbr_cp[e] + (long long)l * p->nao[V] * p->naux[V]);
+      }
+    }
+    p->rows_start[V + 1] = (int)p->row_g.size();
+  }
+  // N buffer offsets: block (V, K, dR) holds [k][s][j][nu]
+  const int nR = p->nR;
+  p->noff.resize((size_t)na * na * nR);
+  long long no = 0;
+  for (int V = 0; V < na; ++V)
+    for (int K = 0; K < na; ++K)
+      for (int r = 0; r < nR; ++r) {
+        p->noff[((size_t)V * na + K) * nR + r] = no;
+        no += (long long)p->nao[K] * 2 * p->nao[V] * p->naux[V];
+      }
+  p->n_elems = no;
+  // N-stage tiles
+  const int M = 2 * nR * p->nb;
+  for (int V = 0; V < na; ++V) {
+    const int NV = p->nao[V] * p->naux[V];
+    for (int n0 = 0; n0 < NV; n0 += 128)
+      for (int m0 = 0; m0 < M; m0 += 128) {
+        p->tileV.push_back(V);
+        p->tileM.push_back(m0);
+        p->tileN.push_back(n0);
+      }
+  }
+  // fused items: atom pairs U <= V (Sec. 3.2 pair set), all R
+  for (int U = 0; U < na; ++U)
+    for (int V = U; V < na; ++V)
+      for (int r = 0; r < nR; ++r) {
+        p->itemU.push_back(U);
+        p->itemV.push_back(V);
+        p->itemR.push_back(r);
+      }
+  // flop model (per tau, times ntau)
+  double fN = 0, fX = 0, fMZ = 0, fChi = 0, eN = 0, eFused = 0;
+  for (int V = 0; V < na; ++V) fN += 2.0 * nR * 2.0 * p->naux[V] * p->nao[V] * p->nb * (double)S[V];
+  eN = fN;
+  for (int U = 0; U < na; ++U)
+    for (int V = U; V < na; ++V) {
+      const double nU = p->nao[U], aU = p->naux[U], nV = p->nao[V], aV = p->naux[V];
+      fX += 2.0 * nR * 2.0 * nU * aV * nV * (double)S[V];
+      fMZ += nR * 8.0 * nU * nV * aV * (double)S[U];
+      fChi += nR * 2.0 * aU * aV * nU * (double)S[U];
+      eFused += nR * (2.0 * nU * 2.0 * nV * aV * (double)S[U] + 2.0 * aU * aV * nU * (double)S[U] +
+                      2.0 * aU * aV * 2.0 * nU * nV);
+    }
+  p->alg_flops = ntau * (fN + fX + fMZ + fChi);
+  p->exec_flops = ntau * (eN + eFused);
+  p->stage_alg[0] = ntau * fN;
+  p->stage_alg[1] = ntau * (fX + fMZ + fChi);
+  p->stage_exec[0] = ntau * eN;
+  p->stage_exec[1] = ntau * eFused;
+
+  // device tables: one allocation, 256-byte aligned sections
+  struct Sec {
+    const void *src;
+    size_t bytes;
+    size_t off;
+  };
+  std::vector<Sec> secs;
+  size_t tot = 0;
+  auto add = [&](const void *src, size_t bytes) {
+    secs.push_back({src, bytes, tot});
+    tot = align_up(tot + std::max<size_t>(bytes, 1));
+    return secs.size() - 1;
+  };
+  const size_t s_nao = add(p->nao.data(), na * 4), s_naux = add(p->naux.data(), na * 4),
+               s_aoo = add(p->ao_off.data(), na * 4), s_auxo = add(p->aux_off.data(), na * 4),
+               s_aoa = add(p->atom_of_ao.data(), p->nb * 4), s_ns = add(p->nbr_start.data(), (na + 1) * 4),
+               s_nK = add(p->nbr_K.data(), nblk * 4), s_nR1 = add(p->nbr_R1.data(), nblk * 4),
+               s_ncp = add(p->nbr_cp.data(), nblk * 8), s_rs = add(p->rows_start.data(), (na + 1) * 4),
+               s_rg = add(p->row_g.data(), p->row_g.size() * 4), s_rdl = add(p->row_dl.data(), p->row_dl.size() * 4),
+               s_rcp = add(p->row_cp.data(), p->row_cp.size() * 8), s_noff = add(p->noff.data(), p->noff.size() * 8),
+               s_tV = add(p->tileV.data(), p->tileV.size() * 4), s_tM = add(p->tileM.data(), p->tileM.size() * 4),
+               s_tN = add(p->tileN.data(), p->tileN.size() * 4), s_iU = add(p->itemU.data(), p->itemU.size() * 4),
+               s_iV = add(p->itemV.data(), p->itemV.size() * 4), s_iR = add(p->itemR.data(), p->itemR.size() * 4),
+               s_pin = add(p->in_off.data(), nblk * 8), s_pout = add(p->out_off.data(), nblk * 8),
+               s_pa = add(p->blk_a.data(), nblk * 4), s_pni = add(p->blk_ni.data(), nblk * 4),
+               s_pnk = add(p->blk_nk.data(), nblk * 4);
+  hipError_t he = hipSetDevice(ctx->device);
+  if (he == hipSuccess) he = hipMalloc(&p->dtab, tot);
+  if (he != hipSuccess) {
+    delete p;
+    return fail(ctx, RPA_ERR_HIP, std::string("plan tables: ") + hipGetErrorString(he));
+  }
+  std::vector<char> host(tot, 0);
+  for (auto &s : secs)
+    if (s.bytes) std::memcpy(host.data() + s.off, s.src, s.bytes);
+  he = hipMemcpy(p->dtab, host.data(), tot, hipMemcpyHostToDevice);
+  if (he != hipSuccess) {
+    hipFree(p->dtab);
+    delete p;
+    return fail(ctx, RPA_ERR_HIP, std::string("plan tables copy: ") + hipGetErrorString(he));
+  }
+  char *d = (char *)p->dtab;
+  auto I32 = [&](size_t s) { return (const int *)(d + secs[s].off); };
+  auto I64 = [&](size_t s) { return (const long long *)(d + secs[s].off); };
+  Chi0Tables &tb = p->tb;
+  tb.nao = I32(s_nao);
+  tb.naux = I32(s_naux);
+  tb.ao_off = I32(s_aoo);
+  tb.aux_off = I32(s_auxo);
+  tb.atom_of_ao = I32(s_aoa);
+  tb.nbr_start = I32(s_ns);
+  tb.nbr_K = I32(s_nK);
+  tb.nbr_R1 = I32(s_nR1);
+  tb.nbr_cp = I64(s_ncp);
+  tb.rows_start = I32(s_rs);
+  tb.row_g = I32(s_rg);
+  tb.row_dl = I32(s_rdl);
+  tb.row_cp = I64(s_rcp);
+  tb.noff = I64(s_noff);
+  tb.natoms = na;
+  tb.nb = p->nb;
+  tb.nauxtot = p->nauxtot;
+  tb.nR = nR;
+  tb.bvk = p->bvk;
+  p->tiles = NTiles{I32(s_tV), I32(s_tM), I32(s_tN), (int)p->tileV.size()};
+  p->items = PairItems{I32(s_iU), I32(s_iV), I32(s_iR), (int)p->itemU.size()};
+  p->pack = PackTables{I64(s_pin), I64(s_pout), I32(s_pa), I32(s_pni), I32(s_pnk), nblk};
+
+  // workspace: packed C, converted G (FP32), N buffer for one tau
+  const size_t es = precision == RPA_FP64 ? 8 : 4;
+  p->ws_cp = 0;
+  p->ws_g = align_up(p->cp_elems * es);
+  const size_t gbytes = precision == RPA_FP32 ? 2 * (size_t)nR * p->nb * p->nb * 4 : 0;
+  p->ws_n = align_up(p->ws_g + gbytes);
+  p->ws_total = align_up(p->ws_n + (size_t)p->n_elems * es);
+  *workspace_bytes = p->ws_total;
+  *out = p;
+  return RPA_OK;
+}
+
+int rpa_plan_destroy(rpa_plan *p) {
+  if (!p) return RPA_ERR_ARG;
+  if (p->dtab) {
+    // the tables may still be read by queued kernels of this plan
+    hipSetDevice(p->device);
+    hipDeviceSynchronize();
+    hipFree(p->dtab);
+  }
+  delete p;
+  return RPA_OK;
+}
+
+int rpa_plan_flops(const rpa_plan *p, double *alg, double *exec) {
+  if (!p || !alg || !exec) return RPA_ERR_ARG;
+  *alg = p->alg_flops;
+  *exec = p->exec_flops;
+  return RPA_OK;
+}
+
+int rpa_plan_stage_flops(const rpa_plan *p, int stage, double *alg, double *exec) {
+  if (!p || !alg || !exec || stage < 0 || stage > 1) return RPA_ERR_ARG;
+  *alg = p->stage_alg[stage];
+  *exec = p->stage_exec[stage];
+  return RPA_OK;
+}
+
+int rpa_profile(rpa_ctx *ctx, int enable) {
+  if (!ctx) return RPA_ERR_ARG;
+  int rc = drain_profile(ctx);
+  ctx->totals.clear();
+  ctx->profile = enable != 0;
+  return rc;
+}
+
+int rpa_profile_read(rpa_ctx *ctx, const char *kernel, double *total_ms, int *launches) {
+  if (!ctx || !kernel || !total_ms || !launches) return RPA_ERR_ARG;
+  if (drain_profile(ctx) != RPA_OK) return fail(ctx, RPA_ERR_HIP, "event timing failed");
+  auto it = ctx->totals.find(kernel);
+  *total_ms = it == ctx->totals.end() ? 0.0 : it->second.first;
+  *launches = it == ctx->totals.end() ? 0 : it->second.second;
+  return RPA_OK;
+}
+
+int build_chi0_tau(rpa_plan *p, double spin_factor, const double *G_occ, const double *G_un, const double *C,
+                   void *workspace, size_t workspace_bytes, double *chi0_tau) {
+  if (!p) return RPA_ERR_ARG;
+  rpa_ctx *ctx = p->ctx;
+  if (!G_occ || !G_un || !chi0_tau || !workspace || (p->nblk > 0 && !C))
+    return fail(ctx, RPA_ERR_ARG, "null pointer");
+  if (workspace_bytes < p->ws_total)
+    return fail(ctx, RPA_ERR_WORKSPACE, "workspace smaller than rpa_plan_create reported");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  hipStream_t s = ctx->stream;
+  char *ws = (char *)workspace;
+  const size_t gstride = (size_t)p->nR * p->nb * p->nb;
+  const size_t chistride = (size_t)p->nR * p->nauxtot * p->nauxtot;
+  const double negs = -spin_factor;
+  if (p->prec == RPA_FP64) {
+    double *Cp = (double *)(ws + p->ws_cp);
+    double *Nb = (double *)(ws + p->ws_n);
+    {
+      Timed tm(ctx, "pack_c");
+      HIP_TRY(ctx, launch_pack_c<double>(p->pack, C, Cp, p->maxblk, s));
+    }
+    for (int t = 0; t < p->ntau; ++t) {
+      const double *go = G_occ + t * gstride, *gu = G_un + t * gstride;
+      {
+        Timed tm(ctx, "nstage");
+        HIP_TRY(ctx, launch_nstage<double>(p->tb, p->tiles, go, gu, Cp, Nb, s));
+      }
+      {
+        Timed tm(ctx, "fused");
+        HIP_TRY(ctx, launch_fused<double>(p->tb, p->items, go, gu, Cp, Nb, negs, chi0_tau + t * chistride, s));
+      }
+    }
+  } else {
+    float *Cp = (float *)(ws + p->ws_cp);
+    float *Gc = (float *)(ws + p->ws_g);
+    float *Nb = (float *)(ws + p->ws_n);
+    {
+      Timed tm(ctx, "pack_c");
+      HIP_TRY(ctx, launch_pack_c<float>(p->pack, C, Cp, p->maxblk, s));
+    }
+    for (int t = 0; t < p->ntau; ++t) {
+      {
+        Timed tm(ctx, "convert_g");
+        HIP_TRY(ctx, launch_convert_g(G_occ + t * gstride, Gc, gstride, s));
+        HIP_TRY(ctx, launch_convert_g(G_un + t * gstride, Gc + gstride, gstride, s));
+      }
+      {
+        Timed tm(ctx, "nstage");
+        HIP_TRY(ctx, launch_nstage<float>(p->tb, p->tiles, Gc, Gc + gstride, Cp, Nb, s));
+      }
+      {
+        Timed tm(ctx, "fused");
+        HIP_TRY(ctx, launch_fused<float>(p->tb, p->items, Gc, Gc + gstride, Cp, Nb, negs, chi0_tau + t * chistride, s));
+      }
+    }
+  }
+  return RPA_OK;
+}
+
+int chi0_tau_to_omega(rpa_ctx *ctx, int ntau, int nomega, size_t n, const double *gamma_cos,
+                      const double *chi0_tau, double *chi0_omega) {
+  if (!ctx) return RPA_ERR_ARG;
+  if (!gamma_cos || !chi0_tau || !chi0_omega) return fail(ctx, RPA_ERR_ARG, "null pointer");
+  if (ntau <= 0 || nomega <= 0 || ntau > 64 || nomega > 64)
+    return fail(ctx, RPA_ERR_ARG, "ntau and nomega must be in [1, 64]");
+  if (n == 0) return RPA_OK;
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  HIP_TRY(ctx, hipMemcpyAsync(ctx->params, gamma_cos, sizeof(double) * ntau * nomega, hipMemcpyHostToDevice,
+                              ctx->stream));
+  Timed tm(ctx, "cos_transform");
+  HIP_TRY(ctx, launch_cos_transform(ctx->params, ntau, nomega, n, chi0_tau, chi0_omega, ctx->stream));
+  return RPA_OK;
+}
+
+int chi0_R_to_q(rpa_ctx *ctx, const int mesh[3], int nbatch, size_t m, int nq, const double *q_frac,
+                const double *chi0_R, double *chi0_q) {
+  if (!ctx) return RPA_ERR_ARG;
+  if (!mesh || !q_frac || !chi0_R || !chi0_q) return fail(ctx, RPA_ERR_ARG, "null pointer");
+  if (nbatch <= 0 || nq <= 0 || mesh[0] <= 0 || mesh[1] <= 0 || mesh[2] <= 0)
+    return fail(ctx, RPA_ERR_ARG, "sizes must be positive");
+  const int nR = mesh[0] * mesh[1] * mesh[2];
+  if ((size_t)2 * nq * nR * sizeof(double) > 64 * 1024)
+    return fail(ctx, RPA_ERR_UNSUPPORTED, "nq * nR must not exceed 4096");
+  if (m == 0) return RPA_OK;
+  // phases exp(2 pi i q . n_R), the fractional part of q . n_R reduced before the 2 pi
+  std::vector<double> ph((size_t)2 * nq * nR);
+  for (int q = 0; q < nq; ++q)
+    for (int r = 0; r < nR; ++r) {
+      const int n0 = r / (mesh[1] * mesh[2]), n1 = (r / mesh[2]) % mesh[1], n2 = r % mesh[2];
+      double x = q_frac[3 * q] * n0 + q_frac[3 * q + 1] * n1 + q_frac[3 * q + 2] * n2;
+      x -= std::floor(x);
+      ph[((size_t)q * nR + r) * 2] = std::cos(2.0 * M_PI * x);
+      ph[((size_t)q * nR + r) * 2 + 1] = std::sin(2.0 * M_PI * x);
+    }
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  HIP_TRY(ctx, hipMemcpyAsync(ctx->params, ph.data(), ph.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+  Timed tm(ctx, "r2q");
+  HIP_TRY(ctx, launch_r2q(ctx->params, nR, nq, nbatch, m, chi0_R, chi0_q, ctx->stream));
+  return RPA_OK;
+}
+
+
+size_t rpa_ec_workspace_size(int n, int nq, int nomega) {
+  if (n <= 0 || nq <= 0 || nomega <= 0) return 0;
+  return ec_layout(n, nq, nomega, nomega).total;
+}
+
+int rpa_correlation_energy(rpa_ctx *ctx, int n, int nq, int nomega, const double *womega, const double *chi0_q,
+                           const double *v_q, void *workspace, size_t workspace_bytes, double *Ec, double *Ec_q) {
+  if (!ctx) return RPA_ERR_ARG;
+  if (!womega || !chi0_q || !v_q || !workspace || !Ec) return fail(ctx, RPA_ERR_ARG, "null pointer");
+  if (n <= 0 || nq <= 0 || nomega <= 0) return fail(ctx, RPA_ERR_ARG, "sizes must be positive");
+  int cw = nomega;
+  while (cw > 1 && ec_layout(n, nq, nomega, cw).total > workspace_bytes) --cw;
+  const EcLayout l = ec_layout(n, nq, nomega, cw);
+  if (l.total > workspace_bytes)
+    return fail(ctx, RPA_ERR_WORKSPACE, "workspace smaller than rpa_ec_workspace_size(n, nq, 1)");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  hipStream_t s = ctx->stream;
+  char *ws = (char *)workspace;
+  double *L = (double *)(ws + l.L), *T = (double *)(ws + l.T), *B = (double *)(ws + l.B),
+         *W = (double *)(ws + l.W), *trB = (double *)(ws + l.trB), *f = (double *)(ws + l.f),
+         *ecq = (double *)(ws + l.ecq), *wdev = (double *)(ws + l.w);
+  int *flags = (int *)(ws + l.flags);
+  const size_t mat = (size_t)n * n * 2;   // doubles per complex matrix
+  std::unique_ptr<Timed> tm(new Timed(ctx, "ec_stage"));   // closed after the quadrature
+  HIP_TRY(ctx, launch_fill_int(flags, (size_t)(nq + nq * nomega), 0, s));
+  HIP_TRY(ctx, hipMemcpyAsync(wdev, womega, nomega * 8, hipMemcpyHostToDevice, s));
+  for (int q = 0; q < nq; ++q) {
+    HIP_TRY(ctx, hipMemcpyAsync(L, v_q + q * mat, mat * 8, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(ctx, launch_cholesky(L, mat, n, 1, W, flags, q, s));
+    HIP_TRY(ctx, launch_zero_upper(L, mat, n, 1, s));
+    for (int k0 = 0; k0 < nomega; k0 += cw) {
+      const int nb = std::min(cw, nomega - k0);
+      // T = chi(q, k) L   (L lower triangular: k >= column of the tile)
+      ZgemmArgs g{};
+      g.M = n;
+      g.N = n;
+      g.K = n;
+      g.A = chi0_q + ((size_t)k0 * nq + q) * mat;
+      g.lda = n;
+      g.strideA = (long long)nq * mat;
+      g.opA = 0;
+      g.B = L;
+      g.ldb = n;
+      g.strideB = 0;
+      g.opB = 0;
+      g.C = T;
+      g.ldc = n;
+      g.strideC = mat;
+      g.alpha = 1.0;
+      g.beta = 0.0;
+      g.lower_only = 0;
+      g.kmode = 1;
+      HIP_TRY(ctx, launch_zgemm(g, nb, s));
+      // B = L^H T, lower triangle only (L^H upper triangular: k >= row of the tile)
+      ZgemmArgs h{};
+      h.M = n;
+      h.N = n;
+      h.K = n;
+      h.A = L;
+      h.lda = n;
+      h.strideA = 0;
+      h.opA = 1;
+      h.B = T;
+      h.ldb = n;
+      h.strideB = mat;
+      h.opB = 0;
+      h.C = B;
+      h.ldc = n;
+      h.strideC = mat;
+      h.alpha = 1.0;
+      h.beta = 0.0;
+      h.lower_only = 1;
+      h.kmode = 2;
+      HIP_TRY(ctx, launch_zgemm(h, nb, s));
+      double *trq = trB + (size_t)q * nomega + k0;
+      HIP_TRY(ctx, launch_trace_identity_minus(B, mat, n, nb, trq, s));
+      HIP_TRY(ctx, launch_cholesky(B, mat, n, nb, W, flags, nq + q * nomega + k0, s));
+      HIP_TRY(ctx, launch_logdet(B, mat, n, nb, trq, f + (size_t)q * nomega + k0, flags, nq + q * nomega + k0, s));
+    }
+  }
+  HIP_TRY(ctx, launch_quadrature(f, wdev, nq, nomega, ecq, s));
+  tm.reset();
+  std::vector<int> hflags(nq + nq * nomega);
+  std::vector<double> hecq(nq + 1);
+  HIP_TRY(ctx, hipMemcpyAsync(hflags.data(), flags, hflags.size() * 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(ctx, hipMemcpyAsync(hecq.data(), ecq, hecq.size() * 8, hipMemcpyDeviceToHost, s));
+  HIP_TRY(ctx, hipStreamSynchronize(s));
+  for (int q = 0; q < nq; ++q)
+    if (hflags[q]) return fail(ctx, RPA_ERR_NOT_HPD, "v(q) is not Hermitian positive definite at q index " + std::to_string(q));
+  for (int q = 0; q < nq; ++q)
+    for (int k = 0; k < nomega; ++k) {
+      const int fl = hflags[nq + q * nomega + k];
+      if (fl == 1)
+        return fail(ctx, RPA_ERR_NOT_HPD, "1 - L^H chi L is not positive definite at q index " + std::to_string(q) +
+                                              ", omega index " + std::to_string(k));
+      if (fl == 2)
+        return fail(ctx, RPA_ERR_NONFINITE, "non-finite log-determinant at q index " + std::to_string(q) +
+                                                ", omega index " + std::to_string(k));
+    }
+  *Ec = hecq[nq];
+  if (Ec_q)
+    for (int q = 0; q < nq; ++q) Ec_q[q] = hecq[q];
+  return RPA_OK;
+}
+
+}  // extern "C"

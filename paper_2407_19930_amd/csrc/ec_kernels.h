@@ -1,0 +1,34 @@
+// Launchers of the correlation-energy stage (complex FP64).
+#pragma once
+
+#include "common.h"
+
+// C[b] = alpha op(A[b]) op(B[b]) + beta C[b]; complex interleaved, row-major, leading
+// dimensions and batch strides in complex elements / doubles as named.
+struct ZgemmArgs {
+  int M, N, K;
+  const double *A;
+  long long lda, strideA;   // lda in complex elements, stride in doubles
+  int opA;                  // 0: A, 1: A^H
+  const double *B;
+  long long ldb, strideB;
+  int opB;                  // 0: B, 1: B^H
+  double *C;
+  long long ldc, strideC;
+  double alpha, beta;
+  int lower_only;           // skip output tiles strictly above the diagonal
+  int kmode;                // 0: all k; 1: k >= first column of the tile (op(B) lower
+                            // triangular); 2: k >= first row of the tile (op(A) upper triangular)
+};
+
+hipError_t launch_zgemm(const ZgemmArgs &g, int batch, hipStream_t s);
+hipError_t launch_cholesky(double *A, size_t stride, int n, int batch, double *Wscratch, int *flags, int flag_base,
+                           hipStream_t s);
+hipError_t launch_zero_upper(double *A, size_t stride, int n, int batch, hipStream_t s);
+hipError_t launch_trace_identity_minus(double *B, size_t stride, int n, int batch, double *trB, hipStream_t s);
+hipError_t launch_logdet(const double *A, size_t stride, int n, int batch, const double *trB, double *f, int *flags,
+                         int flag_base, hipStream_t s);
+hipError_t launch_fill_int(int *p, size_t n, int v, hipStream_t s);
+hipError_t launch_quadrature(const double *f, const double *w, int nq, int nomega, double *ecq, hipStream_t s);
+
+constexpr int kCholBlock = 32;

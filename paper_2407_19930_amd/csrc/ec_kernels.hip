@@ -1,0 +1,408 @@
+// Correlation-energy stage (Sec. 2, E_c^RPA with Tr ln = ln det), FP64 complex:
+//   per q: v(q) = L L^H (blocked Cholesky);  per (q, omega): B = L^H chi L,
+//   f = ln det(I - B) + Tr B = 2 sum_i ln Re(L_A)_ii + Tr B with I - B = L_A L_A^H.
+// Kernels: batched complex GEMM on MFMA f64 (4 real products per complex tile),
+// blocked right-looking Cholesky (diagonal block in LDS, triangular solve by the
+// explicit inverse of the diagonal factor, Hermitian rank-k update by the GEMM),
+// trace / identity-minus, log-diagonal and quadrature reductions.
+#include "ec_kernels.h"
+
+namespace {
+
+constexpr int ZB = 64, ZK = 16, ZT = 256;
+
+__global__ __launch_bounds__(ZT) void zgemm_kernel(ZgemmArgs g) {
+  __shared__ double Ar[2][ZK][ZB], Ai[2][ZK][ZB], Br[2][ZK][ZB], Bi[2][ZK][ZB];
+  const int n0 = blockIdx.x * ZB, m0 = blockIdx.y * ZB, bz = blockIdx.z;
+  if (g.lower_only && n0 > m0 + ZB - 1) return;
+  const double *A = g.A + (size_t)bz * g.strideA;
+  const double *B = g.B + (size_t)bz * g.strideB;
+  double *C = g.C + (size_t)bz * g.strideC;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = w >> 1, wn = w & 1, col = lane & 15, grp = lane >> 4;
+
+  int kbeg = 0;
+  if (g.kmode == 1) kbeg = n0;
+  if (g.kmode == 2) kbeg = m0;
+  kbeg = (kbeg / ZK) * ZK;
+
+  double2 ra[4], rb[4];
+  auto ld = [&](const double *P, size_t idx) -> double2 { return reinterpret_cast<const double2 *>(P)[idx]; };
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      double2 va = make_double2(0.0, 0.0), vb = make_double2(0.0, 0.0);
+      if (g.opA == 0) {
+        const int kk = tid & 15, row = (tid >> 4) + 16 * e;
+        if (m0 + row < g.M && k0 + kk < g.K) va = ld(A, (size_t)(m0 + row) * g.lda + k0 + kk);
+      } else {
+        const int row = tid & 63, kk = (tid >> 6) + 4 * e;
+        if (m0 + row < g.M && k0 + kk < g.K) {
+          va = ld(A, (size_t)(k0 + kk) * g.lda + m0 + row);
+          va.y = -va.y;
+        }
+      }
+      if (g.opB == 0) {
+        const int cc = tid & 63, kk = (tid >> 6) + 4 * e;
+        if (n0 + cc < g.N && k0 + kk < g.K) vb = ld(B, (size_t)(k0 + kk) * g.ldb + n0 + cc);
+      } else {
+        const int kk = tid & 15, cc = (tid >> 4) + 16 * e;
+        if (n0 + cc < g.N && k0 + kk < g.K) {
+          vb = ld(B, (size_t)(n0 + cc) * g.ldb + k0 + kk);
+          vb.y = -vb.y;
+        }
+      }
+      ra[e] = va;
+      rb[e] = vb;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      int row, kk;
+      if (g.opA == 0) {
+        kk = tid & 15;
+        row = (tid >> 4) + 16 * e;
+      } else {
+        row = tid & 63;
+        kk = (tid >> 6) + 4 * e;
+      }
+      Ar[buf][kk][row] = ra[e].x;
+      Ai[buf][kk][row] = ra[e].y;
+      int cc;
+      if (g.opB == 0) {
+        cc = tid & 63;
+        kk = (tid >> 6) + 4 * e;
+      } else {
+        kk = tid & 15;
+        cc = (tid >> 4) + 16 * e;
+      }
+      Br[buf][kk][cc] = rb[e].x;
+      Bi[buf][kk][cc] = rb[e].y;
+    }
+  };
+
+  d4 accR[2][2], accI[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) accR[a][b] = accI[a][b] = Mfma<double>::zero();
+
+  const int nk = g.K > kbeg ? (g.K - kbeg + ZK - 1) / ZK : 0;
+  if (nk > 0) {
+    load(kbeg);
+    store(0);
+  }
+  __syncthreads();
+  for (int it = 0; it < nk; ++it) {
+    const int cur = it & 1;
+    if (it + 1 < nk) load(kbeg + (it + 1) * ZK);
+#pragma unroll
+    for (int ks = 0; ks < ZK / 4; ++ks) {
+      const int kk = ks * 4 + grp;
+      double ar[2], ai[2], br[2], bi[2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        ar[q] = Ar[cur][kk][wm * 32 + q * 16 + col];
+        ai[q] = Ai[cur][kk][wm * 32 + q * 16 + col];
+        br[q] = Br[cur][kk][wn * 32 + q * 16 + col];
+        bi[q] = Bi[cur][kk][wn * 32 + q * 16 + col];
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          accR[a][b] = Mfma<double>::fma(ar[a], br[b], accR[a][b]);
+          accR[a][b] = Mfma<double>::fma(-ai[a], bi[b], accR[a][b]);
+          accI[a][b] = Mfma<double>::fma(ar[a], bi[b], accI[a][b]);
+          accI[a][b] = Mfma<double>::fma(ai[a], br[b], accI[a][b]);
+        }
+    }
+    if (it + 1 < nk) store(cur ^ 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = m0 + wm * 32 + a * 16 + Mfma<double>::row(grp, r);
+        const int j = n0 + wn * 32 + b * 16 + col;
+        if (i < g.M && j < g.N) {
+          double2 *p = reinterpret_cast<double2 *>(C) + (size_t)i * g.ldc + j;
+          double2 o = make_double2(g.alpha * accR[a][b][r], g.alpha * accI[a][b][r]);
+          if (g.beta != 0.0) {
+            const double2 c = *p;
+            o.x += g.beta * c.x;
+            o.y += g.beta * c.y;
+          }
+          *p = o;
+        }
+      }
+}
+
+// ---- Cholesky pieces (block width CB) ----
+constexpr int CB = 32;
+
+// Factor the CB x CB diagonal block at (p, p) of matrix blockIdx.x in LDS; write the
+// factor back (lower triangle) and W = (L11^{-1})^H for the panel solve; flag failures.
+__global__ __launch_bounds__(256) void chol_diag_kernel(double *A, size_t stride, int n, int p, double *Wout,
+                                                        int *flags, int flag_base) {
+  __shared__ double2 L[CB][CB + 1];
+  __shared__ double2 X[CB][CB + 1];
+  __shared__ int bad;
+  const int mtx = blockIdx.x;
+  double2 *M = reinterpret_cast<double2 *>(A + (size_t)mtx * stride);
+  const int b = min(CB, n - p);
+  const int tid = threadIdx.x;
+  if (tid == 0) bad = 0;
+  for (int e = tid; e < CB * CB; e += blockDim.x) {
+    const int i = e / CB, j = e % CB;
+    L[i][j] = (i < b && j < b && j <= i) ? M[(size_t)(p + i) * n + p + j] : make_double2(0.0, 0.0);
+    X[i][j] = make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  for (int j = 0; j < b; ++j) {
+    if (tid == 0) {
+      const double d = L[j][j].x;
+      if (!(d > 0.0) || !isfinite(d)) {
+        bad = 1;
+        L[j][j] = make_double2(1.0, 0.0);
+      } else {
+        L[j][j] = make_double2(sqrt(d), 0.0);
+      }
+    }
+    __syncthreads();
+    const double inv = 1.0 / L[j][j].x;
+    for (int i = j + 1 + tid; i < b; i += blockDim.x) {
+      L[i][j].x *= inv;
+      L[i][j].y *= inv;
+    }
+    __syncthreads();
+    // trailing update of the lower triangle: L[i][k] -= L[i][j] conj(L[k][j]), j < k <= i
+    for (int e = tid; e < CB * CB; e += blockDim.x) {
+      const int i = e / CB, k = e % CB;
+      if (k > j && k <= i && i < b) {
+        const double2 a = L[i][j], c = L[k][j];
+        L[i][k].x -= a.x * c.x + a.y * c.y;
+        L[i][k].y -= a.y * c.x - a.x * c.y;
+      }
+    }
+    __syncthreads();
+  }
+  // X = L^{-1} by forward substitution, one column per thread
+  if (tid < b) {
+    const int c = tid;
+    for (int i = c; i < b; ++i) {
+      double2 s = make_double2(i == c ? 1.0 : 0.0, 0.0);
+      for (int k = c; k < i; ++k) {
+        const double2 l = L[i][k], x = X[k][c];
+        s.x -= l.x * x.x - l.y * x.y;
+        s.y -= l.x * x.y + l.y * x.x;
+      }
+      const double d = L[i][i].x;
+      X[i][c] = make_double2(s.x / d, s.y / d);
+    }
+  }
+  __syncthreads();
+  double2 *W = reinterpret_cast<double2 *>(Wout) + (size_t)mtx * CB * CB;
+  for (int e = tid; e < CB * CB; e += blockDim.x) {
+    const int i = e / CB, j = e % CB;
+    if (i < b && j <= i) M[(size_t)(p + i) * n + p + j] = L[i][j];
+    // W[r][c] = conj(X[c][r])
+    const double2 x = X[j][i];
+    W[e] = make_double2(x.x, -x.y);
+  }
+  if (tid == 0 && bad) flags[flag_base + mtx] = 1;
+}
+
+// Panel solve A21 <- A21 W for rows [p + CB, n) of every matrix (in place; each workgroup
+// owns 64 whole rows of the panel).
+__global__ __launch_bounds__(256) void chol_trsm_kernel(double *A, size_t stride, int n, int p,
+                                                        const double *Win) {
+  __shared__ double2 W[CB][CB + 1];
+  __shared__ double2 P[64][CB + 1];
+  const int mtx = blockIdx.y;
+  double2 *M = reinterpret_cast<double2 *>(A + (size_t)mtx * stride);
+  const double2 *Wm = reinterpret_cast<const double2 *>(Win) + (size_t)mtx * CB * CB;
+  const int r0 = p + CB + blockIdx.x * 64;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < CB * CB; e += blockDim.x) W[e / CB][e % CB] = Wm[e];
+  for (int e = tid; e < 64 * CB; e += blockDim.x) {
+    const int r = e / CB, c = e % CB;
+    P[r][c] = (r0 + r < n) ? M[(size_t)(r0 + r) * n + p + c] : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  for (int e = tid; e < 64 * CB; e += blockDim.x) {
+    const int r = e / CB, c = e % CB;
+    if (r0 + r >= n) continue;
+    double2 s = make_double2(0.0, 0.0);
+    for (int k = 0; k < CB; ++k) {
+      const double2 a = P[r][k], w = W[k][c];
+      s.x += a.x * w.x - a.y * w.y;
+      s.y += a.x * w.y + a.y * w.x;
+    }
+    M[(size_t)(r0 + r) * n + p + c] = s;
+  }
+}
+
+__global__ void zero_upper_kernel(double *A, size_t stride, int n) {
+  double2 *M = reinterpret_cast<double2 *>(A + (size_t)blockIdx.y * stride);
+  const size_t total = (size_t)n * n;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const size_t i = e / n, j = e % n;
+    if (j > i) M[e] = make_double2(0.0, 0.0);
+  }
+}
+
+// trB[m] = sum_i Re B_ii, then B <- I - B (lower triangle and diagonal).
+__global__ __launch_bounds__(256) void trace_kernel(const double *B, size_t stride, int n, double *trB) {
+  __shared__ double red[256];
+  const double2 *M = reinterpret_cast<const double2 *>(B + (size_t)blockIdx.x * stride);
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) s += M[(size_t)i * n + i].x;
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) trB[blockIdx.x] = red[0];
+}
+
+__global__ void identity_minus_kernel(double *B, size_t stride, int n) {
+  double2 *M = reinterpret_cast<double2 *>(B + (size_t)blockIdx.y * stride);
+  const size_t total = (size_t)n * n;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const size_t i = e / n, j = e % n;
+    if (j <= i) {
+      double2 v = M[e];
+      v.x = (i == j ? 1.0 : 0.0) - v.x;
+      v.y = -v.y;
+      M[e] = v;
+    }
+  }
+}
+
+// f[m] = 2 sum_i ln Re L_ii + trB[m]; flags non-finite results.
+__global__ __launch_bounds__(256) void logdet_kernel(const double *A, size_t stride, int n, const double *trB,
+                                                     double *f, int *flags, int flag_base) {
+  __shared__ double red[256];
+  const double2 *M = reinterpret_cast<const double2 *>(A + (size_t)blockIdx.x * stride);
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) s += log(M[(size_t)i * n + i].x);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double v = 2.0 * red[0] + trB[blockIdx.x];
+    f[blockIdx.x] = v;
+    if (!isfinite(v)) flags[flag_base + blockIdx.x] = 2;
+  }
+}
+
+// ecq[q] = sum_k w_k f[q][k] / (2 pi nq), ecq[nq] = sum_q ecq[q]; one workgroup.
+__global__ __launch_bounds__(256) void quadrature_kernel(const double *f, const double *w, int nq, int nomega,
+                                                         double *ecq) {
+  __shared__ double part[256];
+  const double scale = 1.0 / (2.0 * M_PI * nq);
+  double tot = 0.0;
+  for (int q = threadIdx.x; q < nq; q += blockDim.x) {
+    double s = 0.0;
+    for (int k = 0; k < nomega; ++k) s += w[k] * f[(size_t)q * nomega + k];
+    ecq[q] = s * scale;
+    tot += s * scale;
+  }
+  part[threadIdx.x] = tot;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int i = 0; i < (int)blockDim.x; ++i) t += part[i];
+    ecq[nq] = t;
+  }
+}
+
+__global__ void fill_int_kernel(int *p, size_t n, int v) {
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) p[e] = v;
+}
+
+}  // namespace
+
+hipError_t launch_fill_int(int *p, size_t n, int v, hipStream_t s) {
+  const int blocks = (int)std::min<size_t>((n + 255) / 256, 1024);
+  hipLaunchKernelGGL(fill_int_kernel, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_zgemm(const ZgemmArgs &g, int batch, hipStream_t s) {
+  dim3 grid((g.N + ZB - 1) / ZB, (g.M + ZB - 1) / ZB, batch);
+  hipLaunchKernelGGL(zgemm_kernel, grid, dim3(ZT), 0, s, g);
+  return hipGetLastError();
+}
+
+// In-place lower Cholesky of `batch` n x n complex matrices spaced `stride` doubles apart.
+// Wscratch: batch * CB * CB complex; flags[flag_base + m] set non-zero on failure.
+hipError_t launch_cholesky(double *A, size_t stride, int n, int batch, double *Wscratch, int *flags, int flag_base,
+                           hipStream_t s) {
+  hipError_t err = hipSuccess;
+  for (int p = 0; p < n; p += CB) {
+    hipLaunchKernelGGL(chol_diag_kernel, dim3(batch), dim3(256), 0, s, A, stride, n, p, Wscratch, flags, flag_base);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    const int rest = n - p - CB;
+    if (rest <= 0) break;
+    hipLaunchKernelGGL(chol_trsm_kernel, dim3((rest + 63) / 64, batch), dim3(256), 0, s, A, stride, n, p,
+                       (const double *)Wscratch);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    ZgemmArgs g{};
+    g.M = rest;
+    g.N = rest;
+    g.K = CB;
+    g.A = A + 2 * ((size_t)(p + CB) * n + p);
+    g.lda = n;
+    g.strideA = stride;
+    g.opA = 0;
+    g.B = g.A;
+    g.ldb = n;
+    g.strideB = stride;
+    g.opB = 1;
+    g.C = A + 2 * ((size_t)(p + CB) * n + p + CB);
+    g.ldc = n;
+    g.strideC = stride;
+    g.alpha = -1.0;
+    g.beta = 1.0;
+    g.lower_only = 1;
+    g.kmode = 0;
+    if ((err = launch_zgemm(g, batch, s)) != hipSuccess) return err;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_zero_upper(double *A, size_t stride, int n, int batch, hipStream_t s) {
+  const int blocks = (int)std::min<size_t>(((size_t)n * n + 255) / 256, 4096);
+  hipLaunchKernelGGL(zero_upper_kernel, dim3(blocks, batch), dim3(256), 0, s, A, stride, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_trace_identity_minus(double *B, size_t stride, int n, int batch, double *trB, hipStream_t s) {
+  hipLaunchKernelGGL(trace_kernel, dim3(batch), dim3(256), 0, s, (const double *)B, stride, n, trB);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  const int blocks = (int)std::min<size_t>(((size_t)n * n + 255) / 256, 4096);
+  hipLaunchKernelGGL(identity_minus_kernel, dim3(blocks, batch), dim3(256), 0, s, B, stride, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_logdet(const double *A, size_t stride, int n, int batch, const double *trB, double *f, int *flags,
+                         int flag_base, hipStream_t s) {
+  hipLaunchKernelGGL(logdet_kernel, dim3(batch), dim3(256), 0, s, A, stride, n, trB, f, flags, flag_base);
+  return hipGetLastError();
+}
+
+hipError_t launch_quadrature(const double *f, const double *w, int nq, int nomega, double *ecq, hipStream_t s) {
+  hipLaunchKernelGGL(quadrature_kernel, dim3(1), dim3(256), 0, s, f, w, nq, nomega, ecq);
+  return hipGetLastError();
+}

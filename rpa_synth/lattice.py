@@ -35,7 +35,9 @@ def neighbour_pairs(lattice, frac, rcut):
     margin = np.inf
     for I in range(nat):
         for K in range(nat):
-            d = np.linalg.norm(cart[K] + shifts - cart[I], axis=1)
+            # (tau_K - tau_I) + R: negating the pair negates every rounding exactly, so
+            # d(I, K, R) == d(K, I, -R) bit for bit and the list stays symmetric at ties
+            d = np.linalg.norm((cart[K] - cart[I]) + shifts, axis=1)
             margin = min(margin, float(np.min(np.abs(d - rcut))))
             sel = np.nonzero(d < rcut)[0]
             for s in sel:

@@ -1,0 +1,159 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the same seeded inputs.
+
+Tolerances (stated by the target of the path): FP64 path relative Frobenius error of chi <= 1e-11;
+FP32 path <= 1e-5 and |dE_c| <= 1e-6 Ha/atom."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import chi0 as ochi
+from oracle.energy import correlation_energy, ec_terms_lu
+from oracle.pipeline import ec_from_chi_tau
+from oracle.transforms import cos_transform, fourier_R_to_q
+from tests._util import micro, cfg
+from tests._gpu import gpu_chi_tau, gpu_pipeline, rel
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-11
+FP32_TOL = 1e-5
+
+MICRO = [
+    dict(),                                                                        # 2 atoms, mesh 3x2x1
+    dict(seed=2, natoms=3, nao=(2, 5, 3), naux=(3, 6, 2), mesh=(3, 1, 2)),         # ragged, tiny tiles
+    dict(seed=5, natoms=1, nao=(4,), naux=(5,), mesh=(4, 1, 1), rcut=5.0),         # images fold twice
+    dict(seed=7, natoms=2, nao=(17, 9), naux=(33, 18), mesh=(2, 1, 1), rcut=4.0, edge=4.0),  # >16 NAO, >2 mu tiles
+    dict(seed=8, natoms=2, nao=(32, 1), naux=(128, 1), mesh=(1, 1, 1), rcut=3.5, edge=4.0),  # kernel limits
+]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def oracle_cache():
+    return {}
+
+
+def _oracle_chi(inp, key, cache):
+    if key not in cache:
+        cache[key] = ochi.chi0_alg1(inp)
+    return cache[key]
+
+
+@pytest.mark.parametrize("idx", range(len(MICRO)))
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_chi_tau_micro(idx, precision, oracle_cache):
+    spec = MICRO[idx]
+    inp = micro(**spec)
+    say("case chi_tau micro", idx, precision, spec)
+    ref = _oracle_chi(inp, ("micro", idx), oracle_cache)
+    chi, _, _ = gpu_chi_tau(inp, precision)
+    got = chi.cpu().numpy()
+    err = rel(got, ref)
+    say("  rel err", err)
+    assert np.all(np.isfinite(got))
+    assert err <= (FP64_TOL if precision == "fp64" else FP32_TOL)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_chi_tau_tiny_workload(precision, oracle_cache):
+    inp = cfg(0)
+    say("case chi_tau tiny workload", precision)
+    ref = _oracle_chi(inp, "cfg0", oracle_cache)
+    chi, plan, _ = gpu_chi_tau(inp, precision)
+    got = chi.cpu().numpy()
+    err = rel(got, ref)
+    per_tau = max(rel(got[t], ref[t]) for t in range(inp.ntau))
+    say("  rel err", err, "max per-tau", per_tau, "flops", plan.flops())
+    assert err <= (FP64_TOL if precision == "fp64" else FP32_TOL)
+
+
+def test_transforms_match_oracle_on_same_input():
+    """cosine and R->q transforms of the GPU applied to the oracle's chi(R, tau)."""
+    import torch
+    from paper_2407_19930_amd import Context, chi0_R_to_q, chi0_tau_to_omega
+    inp = micro(**MICRO[1])
+    say("case transforms")
+    ref_tau = ochi.chi0_alg1(inp)
+    ctx = Context(0)
+    x = torch.from_numpy(ref_tau).cuda()
+    nw = len(inp.omega)
+    y = torch.empty((nw,) + ref_tau.shape[1:], dtype=torch.float64, device="cuda")
+    chi0_tau_to_omega(ctx, inp.gamma_cos, x, y)
+    q = torch.empty((nw, len(inp.kfrac)) + ref_tau.shape[2:], dtype=torch.complex128, device="cuda")
+    chi0_R_to_q(ctx, inp.cell.mesh, inp.kfrac, y, q)
+    torch.cuda.synchronize()
+    ref_w = cos_transform(ref_tau, inp.gamma_cos)
+    ref_q = fourier_R_to_q(ref_w, inp.Rvec, inp.kfrac)
+    assert rel(y.cpu().numpy(), ref_w) < 1e-14
+    assert rel(q.cpu().numpy(), ref_q) < 1e-14
+
+
+def test_correlation_energy_matches_lu_on_same_input():
+    """GPU Cholesky log-det route against the oracle's LU route, on the oracle's chi(q, i omega)."""
+    import torch
+    from paper_2407_19930_amd import Context, rpa_correlation_energy, rpa_ec_workspace_size
+    inp = cfg(0)
+    say("case E_c same input")
+    ec_ref, perq_ref, chi_q = ec_from_chi_tau(inp, _oracle_chi(inp, "cfg0", {}))
+    ctx = Context(0)
+    n, nq, nw = inp.nauxtot, len(inp.kfrac), len(inp.omega)
+    ws = torch.empty(rpa_ec_workspace_size(n, nq, nw), dtype=torch.uint8, device="cuda")
+    ec, perq = rpa_correlation_energy(ctx, inp.womega, torch.from_numpy(chi_q).cuda(),
+                                      torch.from_numpy(inp.vq).cuda(), ws)
+    say("  E_c gpu", ec, "oracle", ec_ref)
+    assert ec < 0
+    assert abs(ec - ec_ref) <= 1e-11 * abs(ec_ref)
+    assert np.max(np.abs(perq - perq_ref)) <= 1e-11 * abs(ec_ref)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_pipeline_tiny_workload(precision, oracle_cache):
+    inp = cfg(0)
+    say("case pipeline tiny", precision)
+    ec_ref, _, _ = ec_from_chi_tau(inp, _oracle_chi(inp, "cfg0", oracle_cache))
+    out = gpu_pipeline(inp, precision)
+    d = abs(out["ec"] - ec_ref) / inp.natoms
+    say("  E_c/atom gpu", out["ec"] / inp.natoms, "oracle", ec_ref / inp.natoms, "dE/atom", d)
+    assert d <= (1e-10 if precision == "fp64" else 1e-6)
+
+
+def test_errors_are_reported():
+    import torch
+    from paper_2407_19930_amd import Context, Plan, RpaError, build_chi0_tau, rpa_correlation_energy, \
+        rpa_ec_workspace_size
+    from paper_2407_19930_amd.binding import RPA_ERR_NOT_HPD, RPA_ERR_UNSUPPORTED, RPA_ERR_WORKSPACE
+    inp = micro()
+    ctx = Context(0)
+    say("case error paths")
+    with pytest.raises(RpaError) as e:
+        Plan(ctx, [33], [4], (1, 1, 1), [0], [0], [[0, 0, 0]], [0], 2)
+    assert e.value.code == RPA_ERR_UNSUPPORTED
+    plan = Plan(ctx, inp.nao, inp.naux, inp.cell.mesh, inp.blocks.I, inp.blocks.K, inp.blocks.R, inp.blocks.off,
+                inp.ntau)
+    small = torch.empty(16, dtype=torch.uint8, device="cuda")
+    z = torch.zeros(1, dtype=torch.float64, device="cuda")
+    with pytest.raises(RpaError) as e:
+        build_chi0_tau(plan, 2.0, z, z, z, small, z)
+    assert e.value.code == RPA_ERR_WORKSPACE
+    # a sign-flipped (positive) chi makes 1 - L^H chi L indefinite
+    n, nq, nw = 8, 1, 2
+    chi_q = torch.zeros((nw, nq, n, n), dtype=torch.complex128, device="cuda")
+    chi_q[:, 0] = 3.0 * torch.eye(n, dtype=torch.complex128, device="cuda")
+    vq = torch.eye(n, dtype=torch.complex128, device="cuda").reshape(1, n, n).contiguous()
+    ws = torch.empty(rpa_ec_workspace_size(n, nq, nw), dtype=torch.uint8, device="cuda")
+    with pytest.raises(RpaError) as e:
+        rpa_correlation_energy(ctx, np.ones(nw), chi_q, vq, ws)
+    assert e.value.code == RPA_ERR_NOT_HPD
+
+
+def test_deterministic_bitwise():
+    inp = micro(**MICRO[3])
+    say("case determinism")
+    a, _, ctx = gpu_chi_tau(inp, "fp32")
+    b, _, _ = gpu_chi_tau(inp, "fp32", ctx)
+    assert bool((a == b).all())

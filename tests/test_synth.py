@@ -46,8 +46,12 @@ def test_gap_and_chemical_potential():
     assert vbm < inp.mu < cbm
 
 
-def test_neighbour_list_is_symmetric_and_inside_cutoff():
-    inp = micro(natoms=3, nao=(2, 3, 4), naux=(2, 3, 4), mesh=(2, 2, 2))
+@pytest.mark.parametrize("spec", [dict(natoms=3, nao=(2, 3, 4), naux=(2, 3, 4), mesh=(2, 2, 2)),
+                                  # cutoff equal to the cell edge: images sit exactly on the cutoff
+                                  dict(seed=7, natoms=2, nao=(17, 9), naux=(33, 18), mesh=(2, 1, 1), rcut=4.0,
+                                       edge=4.0)])
+def test_neighbour_list_is_symmetric_and_inside_cutoff(spec):
+    inp = micro(**spec)
     b = inp.blocks
     keys = {(int(i), int(k), tuple(r)) for i, k, r in zip(b.I, b.K, b.R.tolist())}
     for i, k, r in list(keys):
