@@ -141,10 +141,10 @@ def main():
         log("timed step %d done" % i)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
-    kt = {k: ctx.profile_read(k) for k in ("pack_c", "convert_g", "nstage", "fused", "cos_transform", "r2q",
+    kt = {k: ctx.profile_read(k) for k in ("pack_c", "pad_g", "nstage", "fused", "cos_transform", "r2q",
                                            "ec_stage")}
     ctx.profile(False)
-    build_ms = sum(kt[k][0] for k in ("pack_c", "convert_g", "nstage", "fused")) / args.steps
+    build_ms = sum(kt[k][0] for k in ("pack_c", "pad_g", "nstage", "fused")) / args.steps
     ec_ms = sum(kt[k][0] for k in ("cos_transform", "r2q", "ec_stage")) / args.steps
 
     # dominant kernel and its roofline

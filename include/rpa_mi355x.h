@@ -113,7 +113,7 @@ RPA_API int rpa_plan_stage_flops(const rpa_plan *plan, int stage, double *alg_fl
 /* Opt-in kernel timing with HIP events recorded on the context's stream around
  * every launch of the library's kernels.  rpa_profile(ctx, 1) enables and resets,
  * rpa_profile(ctx, 0) disables.  rpa_profile_read waits for the recorded events and
- * returns the summed duration and launch count of one kernel ("pack_c", "convert_g",
+ * returns the summed duration and launch count of one kernel ("pack_c", "pad_g",
  * "nstage", "fused", "cos_transform", "r2q", "ec_stage").  Errors: RPA_ERR_ARG, RPA_ERR_HIP. */
 RPA_API int rpa_profile(rpa_ctx *ctx, int enable);
 RPA_API int rpa_profile_read(rpa_ctx *ctx, const char *kernel, double *total_ms, int *launches);

@@ -85,6 +85,10 @@ int drain_profile(rpa_ctx *ctx) {
 
 }  // namespace
 
+struct PlanGroup {
+  int mt, js, start, count;
+};
+
 struct rpa_plan {
   rpa_ctx *ctx = nullptr;      // must outlive the plan
   int device = 0;
@@ -93,16 +97,19 @@ struct rpa_plan {
   Bvk bvk{1, 1, 1};
   std::vector<int> nao, naux, ao_off, aux_off, atom_of_ao;
   std::vector<long long> in_off, out_off;      // caller block offsets, packed offsets
-  std::vector<int> blk_a, blk_ni, blk_nk;
+  std::vector<int> blk_a, blk_ni, blk_nk, blk_stride;
+  std::vector<int> cp_stride;                   // per atom: packed row length, nao*naux rounded up to 8
+  int nbp = 0;                                  // nb rounded up to 8
   long long cp_elems = 0, maxblk = 0;
   std::vector<int> nbr_start, nbr_K, nbr_R1;
   std::vector<long long> nbr_cp;
-  std::vector<int> rows_start, row_g, row_dl;
-  std::vector<long long> row_cp;
+  std::vector<int> rows_start;
+  std::vector<int4> row_info;
   std::vector<long long> noff;
   long long n_elems = 0;                        // N buffer elements per tau
   std::vector<int> tileV, tileM, tileN;
   std::vector<int> itemU, itemV, itemR;
+  std::vector<PlanGroup> groups;
   double alg_flops = 0, exec_flops = 0;
   double stage_alg[2] = {0, 0}, stage_exec[2] = {0, 0};
   // device tables (one allocation owned by the plan)
@@ -113,6 +120,10 @@ struct rpa_plan {
   PackTables pack{};
   // workspace layout (bytes)
   size_t ws_cp = 0, ws_g = 0, ws_n = 0, ws_total = 0;
+
+  PairItems group_items(const PlanGroup &g) const {
+    return PairItems{items.U + g.start, items.V + g.start, items.R + g.start, g.count};
+  }
 };
 
 // ---- correlation energy ----
@@ -148,6 +159,39 @@ EcLayout ec_layout(int n, int nq, int nomega, int cw) {
   return l;
 }
 }  // namespace
+
+template <typename T>
+static int build_impl(rpa_plan *p, const double *G_occ, const double *G_un, const double *C, char *ws, double negs,
+                      double *chi0_tau) {
+  rpa_ctx *ctx = p->ctx;
+  hipStream_t s = ctx->stream;
+  const size_t gstride = (size_t)p->nR * p->nb * p->nb;
+  const size_t chistride = (size_t)p->nR * p->nauxtot * p->nauxtot;
+  T *Cp = (T *)(ws + p->ws_cp);
+  T *Gp = (T *)(ws + p->ws_g);
+  T *Nb = (T *)(ws + p->ws_n);
+  {
+    Timed tm(ctx, "pack_c");
+    HIP_TRY(ctx, launch_pack_c<T>(p->pack, C, Cp, p->maxblk, s));
+  }
+  for (int t = 0; t < p->ntau; ++t) {
+    {
+      Timed tm(ctx, "pad_g");
+      HIP_TRY(ctx, launch_pad_g<T>(G_occ + t * gstride, G_un + t * gstride, p->nR, p->nb, p->nbp, Gp, s));
+    }
+    {
+      Timed tm(ctx, "nstage");
+      HIP_TRY(ctx, launch_nstage<T>(p->tb, p->tiles, Gp, Cp, Nb, s));
+    }
+    {
+      Timed tm(ctx, "fused");
+      for (const PlanGroup &g : p->groups)
+        HIP_TRY(ctx, launch_fused<T>(p->tb, p->group_items(g), g.mt, g.js, Gp, Cp, Nb, negs, chi0_tau + t * chistride,
+                                     s));
+    }
+  }
+  return RPA_OK;
+}
 
 extern "C" {
 
@@ -194,8 +238,10 @@ int rpa_plan_create(rpa_ctx *ctx, const rpa_cell *cell, const rpa_lri_blocks *bl
   if (cell->natoms <= 0 || !cell->nao || !cell->naux) return fail(ctx, RPA_ERR_ARG, "bad cell");
   if (ntau <= 0) return fail(ctx, RPA_ERR_ARG, "ntau must be positive");
   if (precision != RPA_FP64 && precision != RPA_FP32) return fail(ctx, RPA_ERR_ARG, "unknown precision");
-  for (int d = 0; d < 3; ++d)
+  for (int d = 0; d < 3; ++d) {
     if (cell->mesh[d] <= 0) return fail(ctx, RPA_ERR_ARG, "mesh must be positive");
+    if (cell->mesh[d] > 1023) return fail(ctx, RPA_ERR_UNSUPPORTED, "mesh dimensions must be below 1024");
+  }
   if (blocks->nblk < 0 || (blocks->nblk > 0 && (!blocks->I || !blocks->K || !blocks->R || !blocks->off)))
     return fail(ctx, RPA_ERR_ARG, "bad block list");
 
@@ -231,6 +277,9 @@ int rpa_plan_create(rpa_ctx *ctx, const rpa_cell *cell, const rpa_lri_blocks *bl
   }
   p->nb = p->ao_off[na - 1] + p->nao[na - 1];
   p->nauxtot = p->aux_off[na - 1] + p->naux[na - 1];
+  p->nbp = (p->nb + 7) / 8 * 8;
+  p->cp_stride.resize(na);
+  for (int a = 0; a < na; ++a) p->cp_stride[a] = (p->nao[a] * p->naux[a] + 7) / 8 * 8;
   p->atom_of_ao.resize(p->nb);
   for (int a = 0; a < na; ++a)
     for (int i = 0; i < p->nao[a]; ++i) p->atom_of_ao[p->ao_off[a] + i] = a;
@@ -243,6 +292,7 @@ int rpa_plan_create(rpa_ctx *ctx, const rpa_cell *cell, const rpa_lri_blocks *bl
   p->blk_a.resize(nblk);
   p->blk_ni.resize(nblk);
   p->blk_nk.resize(nblk);
+  p->blk_stride.resize(nblk);
   std::vector<int> fR(nblk);
   long long acc = 0;
   for (int b = 0; b < nblk; ++b) {
@@ -262,7 +312,8 @@ int rpa_plan_create(rpa_ctx *ctx, const rpa_cell *cell, const rpa_lri_blocks *bl
     p->blk_a[b] = p->naux[I];
     p->blk_ni[b] = p->nao[I];
     p->blk_nk[b] = p->nao[K];
-    const long long sz = (long long)p->naux[I] * p->nao[I] * p->nao[K];
+    p->blk_stride[b] = p->cp_stride[I];
+    const long long sz = (long long)p->cp_stride[I] * p->nao[K];   // packed: [k][(i, mu)], padded rows
     p->maxblk = std::max(p->maxblk, sz);
     acc += sz;
   }
@@ -288,13 +339,15 @@ int rpa_plan_create(rpa_ctx *ctx, const rpa_cell *cell, const rpa_lri_blocks *bl
     for (int e = p->nbr_start[V]; e < p->nbr_start[V + 1]; ++e) {
       const int L = p->nbr_K[e];
       S[V] += p->nao[L];
+      int c0, c1, c2;
+      p->bvk.split(p->nbr_R1[e], c0, c1, c2);
       for (int l = 0; l < p->nao[L]; ++l) {
-        p->row_g.push_back(p->ao_off[L] + l);
-        p->row_dl.push_back(p->nbr_R1[e]);
-        p->row_cp.push_back(p->nbr_cp[e] + (long long)l * p->nao[V] * p->naux[V]);
+        const long long cp = p->nbr_cp[e] + (long long)l * p->cp_stride[V];
+        p->row_info.push_back(make_int4(p->ao_off[L] + l, c0 | (c1 << 10) | (c2 << 20), (int)(cp & 0xffffffffLL),
+                                        (int)(cp >> 32)));
       }
     }
-    p->rows_start[V + 1] = (int)p->row_g.size();
+    p->rows_start[V + 1] = (int)p->row_info.size();
   }
   // N buffer offsets: block (V, K, dR) holds [k][s][j][nu]
   const int nR = p->nR;
@@ -308,7 +361,7 @@ int rpa_plan_create(rpa_ctx *ctx, const rpa_cell *cell, const rpa_lri_blocks *bl
       }
   p->n_elems = no;
   // N-stage tiles
-  const int M = 2 * nR * p->nb;
+  const int M = 2 * nR * p->nbp;
   for (int V = 0; V < na; ++V) {
     const int NV = p->nao[V] * p->naux[V];
     for (int n0 = 0; n0 < NV; n0 += 128)
@@ -318,14 +371,32 @@ int rpa_plan_create(rpa_ctx *ctx, const rpa_cell *cell, const rpa_lri_blocks *bl
         p->tileN.push_back(n0);
       }
   }
-  // fused items: atom pairs U <= V (Sec. 3.2 pair set), all R
-  for (int U = 0; U < na; ++U)
-    for (int V = U; V < na; ++V)
-      for (int r = 0; r < nR; ++r) {
-        p->itemU.push_back(U);
-        p->itemV.push_back(V);
-        p->itemR.push_back(r);
-      }
+  // fused items: atom pairs U <= V (Sec. 3.2 pair set), all R; grouped by the kernel's
+  // template classes (mu-tiles of U, O-GEMM steps of V)
+  {
+    std::map<std::pair<int, int>, std::vector<std::pair<int, int>>> groups;
+    for (int U = 0; U < na; ++U)
+      for (int V = U; V < na; ++V) groups[{fused_mt_class(p->naux[U]), fused_js_class(p->nao[V])}].push_back({U, V});
+    for (auto &g : groups) {
+      PlanGroup pg;
+      pg.mt = g.first.first;
+      pg.js = g.first.second;
+      pg.start = (int)p->itemU.size();
+      for (auto &uv : g.second)
+        for (int r = 0; r < nR; ++r) {
+          p->itemU.push_back(uv.first);
+          p->itemV.push_back(uv.second);
+          p->itemR.push_back(r);
+        }
+      pg.count = (int)p->itemU.size() - pg.start;
+      p->groups.push_back(pg);
+    }
+  }
+  for (int a = 0; a < na; ++a)
+    if (p->nbr_start[a + 1] - p->nbr_start[a] > kMaxNbr) {
+      delete p;
+      return fail(ctx, RPA_ERR_UNSUPPORTED, "more than 1024 LRI blocks for one atom");
+    }
   // flop model (per tau, times ntau)
   double fN = 0, fX = 0, fMZ = 0, fChi = 0, eN = 0, eFused = 0;
   for (int V = 0; V < na; ++V) fN += 2.0 * nR * 2.0 * p->naux[V] * p->nao[V] * p->nb * (double)S[V];
@@ -364,14 +435,14 @@ int rpa_plan_create(rpa_ctx *ctx, const rpa_cell *cell, const rpa_lri_blocks *bl
                s_aoa = add(p->atom_of_ao.data(), p->nb * 4), s_ns = add(p->nbr_start.data(), (na + 1) * 4),
                s_nK = add(p->nbr_K.data(), nblk * 4), s_nR1 = add(p->nbr_R1.data(), nblk * 4),
                s_ncp = add(p->nbr_cp.data(), nblk * 8), s_rs = add(p->rows_start.data(), (na + 1) * 4),
-               s_rg = add(p->row_g.data(), p->row_g.size() * 4), s_rdl = add(p->row_dl.data(), p->row_dl.size() * 4),
-               s_rcp = add(p->row_cp.data(), p->row_cp.size() * 8), s_noff = add(p->noff.data(), p->noff.size() * 8),
+               s_ri = add(p->row_info.data(), p->row_info.size() * 16), s_noff = add(p->noff.data(), p->noff.size() * 8),
                s_tV = add(p->tileV.data(), p->tileV.size() * 4), s_tM = add(p->tileM.data(), p->tileM.size() * 4),
                s_tN = add(p->tileN.data(), p->tileN.size() * 4), s_iU = add(p->itemU.data(), p->itemU.size() * 4),
                s_iV = add(p->itemV.data(), p->itemV.size() * 4), s_iR = add(p->itemR.data(), p->itemR.size() * 4),
                s_pin = add(p->in_off.data(), nblk * 8), s_pout = add(p->out_off.data(), nblk * 8),
                s_pa = add(p->blk_a.data(), nblk * 4), s_pni = add(p->blk_ni.data(), nblk * 4),
-               s_pnk = add(p->blk_nk.data(), nblk * 4);
+               s_pnk = add(p->blk_nk.data(), nblk * 4), s_pst = add(p->blk_stride.data(), nblk * 4),
+               s_cst = add(p->cp_stride.data(), na * 4);
   hipError_t he = hipSetDevice(ctx->device);
   if (he == hipSuccess) he = hipMalloc(&p->dtab, tot);
   if (he != hipSuccess) {
@@ -401,24 +472,24 @@ int rpa_plan_create(rpa_ctx *ctx, const rpa_cell *cell, const rpa_lri_blocks *bl
   tb.nbr_R1 = I32(s_nR1);
   tb.nbr_cp = I64(s_ncp);
   tb.rows_start = I32(s_rs);
-  tb.row_g = I32(s_rg);
-  tb.row_dl = I32(s_rdl);
-  tb.row_cp = I64(s_rcp);
+  tb.row_info = (const int4 *)(d + secs[s_ri].off);
   tb.noff = I64(s_noff);
+  tb.cp_stride = I32(s_cst);
   tb.natoms = na;
   tb.nb = p->nb;
+  tb.nbp = p->nbp;
   tb.nauxtot = p->nauxtot;
   tb.nR = nR;
   tb.bvk = p->bvk;
   p->tiles = NTiles{I32(s_tV), I32(s_tM), I32(s_tN), (int)p->tileV.size()};
   p->items = PairItems{I32(s_iU), I32(s_iV), I32(s_iR), (int)p->itemU.size()};
-  p->pack = PackTables{I64(s_pin), I64(s_pout), I32(s_pa), I32(s_pni), I32(s_pnk), nblk};
+  p->pack = PackTables{I64(s_pin), I64(s_pout), I32(s_pa), I32(s_pni), I32(s_pnk), I32(s_pst), nblk};
 
-  // workspace: packed C, converted G (FP32), N buffer for one tau
+  // workspace: packed C, padded G of one tau, N buffer for one tau
   const size_t es = precision == RPA_FP64 ? 8 : 4;
   p->ws_cp = 0;
   p->ws_g = align_up(p->cp_elems * es);
-  const size_t gbytes = precision == RPA_FP32 ? 2 * (size_t)nR * p->nb * p->nb * 4 : 0;
+  const size_t gbytes = 2 * (size_t)nR * p->nbp * p->nbp * es;
   p->ws_n = align_up(p->ws_g + gbytes);
   p->ws_total = align_up(p->ws_n + (size_t)p->n_elems * es);
   *workspace_bytes = p->ws_total;
@@ -478,54 +549,10 @@ int build_chi0_tau(rpa_plan *p, double spin_factor, const double *G_occ, const d
   if (workspace_bytes < p->ws_total)
     return fail(ctx, RPA_ERR_WORKSPACE, "workspace smaller than rpa_plan_create reported");
   HIP_TRY(ctx, hipSetDevice(ctx->device));
-  hipStream_t s = ctx->stream;
   char *ws = (char *)workspace;
-  const size_t gstride = (size_t)p->nR * p->nb * p->nb;
-  const size_t chistride = (size_t)p->nR * p->nauxtot * p->nauxtot;
   const double negs = -spin_factor;
-  if (p->prec == RPA_FP64) {
-    double *Cp = (double *)(ws + p->ws_cp);
-    double *Nb = (double *)(ws + p->ws_n);
-    {
-      Timed tm(ctx, "pack_c");
-      HIP_TRY(ctx, launch_pack_c<double>(p->pack, C, Cp, p->maxblk, s));
-    }
-    for (int t = 0; t < p->ntau; ++t) {
-      const double *go = G_occ + t * gstride, *gu = G_un + t * gstride;
-      {
-        Timed tm(ctx, "nstage");
-        HIP_TRY(ctx, launch_nstage<double>(p->tb, p->tiles, go, gu, Cp, Nb, s));
-      }
-      {
-        Timed tm(ctx, "fused");
-        HIP_TRY(ctx, launch_fused<double>(p->tb, p->items, go, gu, Cp, Nb, negs, chi0_tau + t * chistride, s));
-      }
-    }
-  } else {
-    float *Cp = (float *)(ws + p->ws_cp);
-    float *Gc = (float *)(ws + p->ws_g);
-    float *Nb = (float *)(ws + p->ws_n);
-    {
-      Timed tm(ctx, "pack_c");
-      HIP_TRY(ctx, launch_pack_c<float>(p->pack, C, Cp, p->maxblk, s));
-    }
-    for (int t = 0; t < p->ntau; ++t) {
-      {
-        Timed tm(ctx, "convert_g");
-        HIP_TRY(ctx, launch_convert_g(G_occ + t * gstride, Gc, gstride, s));
-        HIP_TRY(ctx, launch_convert_g(G_un + t * gstride, Gc + gstride, gstride, s));
-      }
-      {
-        Timed tm(ctx, "nstage");
-        HIP_TRY(ctx, launch_nstage<float>(p->tb, p->tiles, Gc, Gc + gstride, Cp, Nb, s));
-      }
-      {
-        Timed tm(ctx, "fused");
-        HIP_TRY(ctx, launch_fused<float>(p->tb, p->items, Gc, Gc + gstride, Cp, Nb, negs, chi0_tau + t * chistride, s));
-      }
-    }
-  }
-  return RPA_OK;
+  if (p->prec == RPA_FP64) return build_impl<double>(p, G_occ, G_un, C, ws, negs, chi0_tau);
+  return build_impl<float>(p, G_occ, G_un, C, ws, negs, chi0_tau);
 }
 
 int chi0_tau_to_omega(rpa_ctx *ctx, int ntau, int nomega, size_t n, const double *gamma_cos,

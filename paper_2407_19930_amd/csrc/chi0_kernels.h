@@ -13,14 +13,15 @@ struct Chi0Tables {
   const int *nbr_K, *nbr_R1;                  // [nblk] second atom, folded lattice vector
   const long long *nbr_cp;                    // [nblk] offset of the packed block [k][i][mu]
   // contraction rows of the N-stage for atom V: r in [rows_start[V], rows_start[V+1])
-  //   row r <-> (neighbour L(dL) of V, NAO l of L)
+  //   row r <-> (neighbour L(dL) of V, NAO l of L); row_info[r] = {G row ao_off[L] + l,
+  //   BvK components of dL packed as d0 | d1 << 10 | d2 << 20, packed-C offset of row
+  //   [l][j][nu] (low, high 32 bits)}
   const int *rows_start;                      // [natoms + 1]
-  const int *row_g;                           // G row index ao_off[L] + l
-  const int *row_dl;                          // folded dL
-  const long long *row_cp;                    // offset of packed row [l][j][nu] (n_V * a_V values)
+  const int4 *row_info;
   // N buffer: block (V, K, dR) at noff[(V * natoms + K) * nR + dR], layout [k][s][j][nu]
   const long long *noff;
-  int natoms, nb, nauxtot, nR;
+  const int *cp_stride;                       // [natoms] packed row stride of atom U's blocks
+  int natoms, nb, nbp, nauxtot, nR;           // nbp: nb rounded up to a multiple of 8
   Bvk bvk;
 };
 
@@ -36,21 +37,27 @@ struct PairItems {   // fused-kernel items: atom pair U <= V and lattice vector 
 
 struct PackTables {  // repack of the caller's LRI blocks
   const long long *in_off, *out_off;
-  const int *a, *ni, *nk;
+  const int *a, *ni, *nk, *stride;
   int nblk;
 };
 
 // launchers (return hipError_t of the launch)
 template <typename T>
 hipError_t launch_pack_c(const PackTables &pt, const double *C, T *Cp, long long maxblk, hipStream_t s);
-hipError_t launch_convert_g(const double *src, float *dst, size_t n, hipStream_t s);
 template <typename T>
-hipError_t launch_nstage(const Chi0Tables &tb, const NTiles &tiles, const T *Gocc, const T *Gun,
-                         const T *Cp, T *Nbuf, hipStream_t s);
+hipError_t launch_pad_g(const double *Gocc, const double *Gun, int nR, int nb, int nbp, T *Gp, hipStream_t s);
 template <typename T>
-hipError_t launch_fused(const Chi0Tables &tb, const PairItems &items, const T *Gocc, const T *Gun,
-                        const T *Cp, const T *Nbuf, double negs, double *chi, hipStream_t s);
+hipError_t launch_nstage(const Chi0Tables &tb, const NTiles &tiles, const T *Gp, const T *Cp, T *Nbuf,
+                         hipStream_t s);
+// Fused kernel for a group of items whose atoms share the template classes
+// mt = fused_mt_class(naux_U) and js = fused_js_class(nao_V).
+int fused_mt_class(int naux);
+int fused_js_class(int nao);
+template <typename T>
+hipError_t launch_fused(const Chi0Tables &tb, const PairItems &items, int mt, int js, const T *Gp, const T *Cp,
+                        const T *Nbuf, double negs, double *chi, hipStream_t s);
 
 // compile-time limits of the kernels
 constexpr int kMaxNao = 32;     // NAOs per atom
 constexpr int kMaxNaux = 128;   // ABFs per atom
+constexpr int kMaxNbr = 1024;   // LRI blocks (neighbours) per atom

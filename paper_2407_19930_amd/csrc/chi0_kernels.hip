@@ -24,53 +24,79 @@ namespace {
 template <typename T>
 __global__ __launch_bounds__(256) void pack_c_kernel(PackTables pt, const double *__restrict__ C,
                                                      T *__restrict__ Cp) {
+  // block b: [mu][i][k] (FP64) -> [k][(i, mu)] with rows padded to stride[b] (zeros)
   const int b = blockIdx.x;
-  const int a = pt.a[b], ni = pt.ni[b], nk = pt.nk[b];
-  const long long total = (long long)a * ni * nk;
+  const int a = pt.a[b], ni = pt.ni[b], nk = pt.nk[b], st = pt.stride[b];
+  const int rowlen = a * ni;
+  const long long total = (long long)nk * st;
   const double *src = C + pt.in_off[b];
   T *dst = Cp + pt.out_off[b];
   for (long long e = (long long)blockIdx.y * blockDim.x + threadIdx.x; e < total;
        e += (long long)gridDim.y * blockDim.x) {
-    const int mu = (int)(e % a);
-    const long long t = e / a;
-    const int i = (int)(t % ni);
-    const int k = (int)(t / ni);
-    dst[e] = (T)src[((long long)mu * ni + i) * nk + k];
+    const int k = (int)(e / st);
+    const int w = (int)(e - (long long)k * st);
+    T v = T(0);
+    if (w < rowlen) {
+      const int i = w / a, mu = w - i * a;
+      v = (T)src[((long long)mu * ni + i) * nk + k];
+    }
+    dst[e] = v;
   }
 }
 
-__global__ __launch_bounds__(256) void convert_g_kernel(const double *__restrict__ src,
-                                                        float *__restrict__ dst, size_t n) {
-  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x)
-    dst[e] = (float)src[e];
+// G^occ, G^un of one tau (FP64, [nR][nb][nb] each) -> Gp[s][R][nbp][nbp] in the compute
+// precision, s = 0 occ, 1 un, zero padding up to nbp (a multiple of 8).
+template <typename T>
+__global__ __launch_bounds__(256) void pad_g_kernel(const double *__restrict__ Gocc, const double *__restrict__ Gun,
+                                                    int nR, int nb, int nbp, T *__restrict__ Gp) {
+  const size_t total = (size_t)2 * nR * nbp * nbp;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const int c = (int)(e % nbp);
+    const size_t t = e / nbp;
+    const int r = (int)(t % nbp);
+    const size_t sR = t / nbp;
+    const int R = (int)(sR % nR), s = (int)(sR / nR);
+    T v = T(0);
+    if (r < nb && c < nb) v = (T)(s ? Gun : Gocc)[((size_t)R * nb + r) * nb + c];
+    Gp[e] = v;
+  }
 }
 
 // ---------------------------------------------------------------------------
 // N-stage: out[(s, dR, k)][(j, nu)] = sum_r A[(s,dR,k)][r] B[r][(j,nu)]
-//   A[(s,dR,k)][r] = G^s[dR - dL(r)][g(r)][k],  B[r][(j,nu)] = Cp[row_cp(r) + j*a_V + nu]
-// 128x128 output tile per workgroup, 4 waves of 64x64, K step 16, LDS double buffer.
-// kSplit: FP32 MFMA partial sums are added into FP64 every kFlush K steps.
+//   A[(s,dR,k)][r] = Gp[s][dR - dL(r)][g(r)][k],  B[r][(j,nu)] = Cp[cp(r) + j*a_V + nu]
+// Rows (s, dR, k) run over the padded NAO range nbp (multiple of 8), so every 8-row chunk
+// lies in one (s, dR) and in one padded G row; packed C rows are padded to a multiple of 8.
+// Each thread loads, per contraction row, 8 consecutive elements of A and of B with 16-byte
+// vector loads.  128x128 output tile, 4 waves of 64x64 (16x16x4 MFMA), K step BK, LDS
+// double buffer with a padded row stride (conflict-free MFMA operand reads).
+// kSplit: FP32 partial sums are added into FP64 every 256 contraction rows.
 // ---------------------------------------------------------------------------
-constexpr int NS_BM = 128, NS_BN = 128, NS_BK = 16, NS_THREADS = 256;
+constexpr int NS_BM = 128, NS_BN = 128, NS_THREADS = 256;
 
-template <typename T, bool kSplit>
-__global__ __launch_bounds__(NS_THREADS) void nstage_kernel(Chi0Tables tb, NTiles tiles,
-                                                            const T *__restrict__ Gocc,
-                                                            const T *__restrict__ Gun,
-                                                            const T *__restrict__ Cp,
-                                                            T *__restrict__ Nbuf) {
+template <typename T> struct alignas(16) Vec16 {
+  T v[16 / sizeof(T)];
+};
+
+template <typename T, bool kSplit, int BK>
+__global__ __launch_bounds__(NS_THREADS) void nstage_kernel(Chi0Tables tb, NTiles tiles, const T *__restrict__ Gp,
+                                                            const T *__restrict__ Cp, T *__restrict__ Nbuf) {
   typedef typename Mfma<T>::acc Acc;
-  constexpr int kFlush = 8;
-  __shared__ T As[2][NS_BK][NS_BM];
-  __shared__ T Bs[2][NS_BK][NS_BN];
+  constexpr int PAD = sizeof(T) == 4 ? 16 : 8;
+  constexpr int RPT = BK / 16;                 // contraction rows per thread and step
+  constexpr int VEC = 16 / sizeof(T);          // elements per 16-byte vector
+  constexpr int NVEC = 8 / VEC;                // vectors per 8-element chunk
+  constexpr int kFlush = 256 / BK;
+  __shared__ __align__(16) T As[2][BK][NS_BM + PAD];
+  __shared__ __align__(16) T Bs[2][BK][NS_BN + PAD];
 
   const int t = blockIdx.x;
   const int V = tiles.V[t], m0 = tiles.m0[t], n0 = tiles.n0[t];
   const int nV = tb.nao[V], aV = tb.naux[V];
-  const int NV = nV * aV;
-  const int nb = tb.nb, nR = tb.nR;
-  const size_t nbnb = (size_t)nb * nb;
-  const int M = 2 * nR * nb;
+  const int NV = nV * aV, NVp = tb.cp_stride[V];
+  const int nbp = tb.nbp, nR = tb.nR, nb = tb.nb;
+  const size_t plane = (size_t)nbp * nbp;
+  const int M = 2 * nR * nbp;
   const int r0 = tb.rows_start[V];
   const int S = tb.rows_start[V + 1] - r0;
 
@@ -78,45 +104,62 @@ __global__ __launch_bounds__(NS_THREADS) void nstage_kernel(Chi0Tables tb, NTile
   const int wm = wave >> 1, wn = wave & 1;
   const int col = lane & 15, grp = lane >> 4;
 
-  // loader coordinates (fixed over the K loop)
-  const int lm = tid & 127, lr = (tid >> 7) * 8;
-  const int m = m0 + lm;
+  // loader coordinates: chunk c of 8 rows/columns, contraction rows rr + 16 q
+  const int c = tid & 15, rr = tid >> 4;
+  const int m = m0 + 8 * c;
   const bool mvalid = m < M;
-  int ss = 0, dR = 0, kk = 0;
+  int ss = 0, d0 = 0, d1 = 0, d2 = 0, kp = 0;
   if (mvalid) {
-    ss = m / (nR * nb);
-    const int rem = m - ss * nR * nb;
-    dR = rem / nb;
-    kk = rem - dR * nb;
+    ss = m / (nR * nbp);
+    const int rem = m - ss * nR * nbp;
+    const int dR = rem / nbp;
+    kp = rem - dR * nbp;
+    tb.bvk.split(dR, d0, d1, d2);
   }
-  const T *Gs = ss ? Gun : Gocc;
-  const int n = n0 + lm;
-  const bool nvalid = n < NV;
+  const int n0m = tb.bvk.n0, n1m = tb.bvk.n1, n2m = tb.bvk.n2;
+  const T *Abase = Gp + (size_t)ss * nR * plane + kp;
+  const int n = n0 + 8 * c;
+  const bool nvalid = n < NVp;
+  const T *Bbase = Cp + n;
 
-  T ra[8], rb[8];
+  Vec16<T> ra[RPT][NVEC], rb[RPT][NVEC];
   auto load = [&](int k0) {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int r = k0 + lr + e;
-      T va = T(0), vb = T(0);
+    for (int q = 0; q < RPT; ++q) {
+      const int r = k0 + rr + 16 * q;
+#pragma unroll
+      for (int v = 0; v < NVEC; ++v)
+#pragma unroll
+        for (int x = 0; x < VEC; ++x) ra[q][v].v[x] = rb[q][v].v[x] = T(0);
       if (r < S) {
-        const int rr = r0 + r;
+        const int4 ri = tb.row_info[r0 + r];
         if (mvalid) {
-          const int Rp = tb.bvk.sub(dR, tb.row_dl[rr]);
-          va = Gs[(size_t)Rp * nbnb + (size_t)tb.row_g[rr] * nb + kk];
+          int c0 = d0 - (ri.y & 1023), c1 = d1 - ((ri.y >> 10) & 1023), c2 = d2 - (ri.y >> 20);
+          c0 += c0 < 0 ? n0m : 0;
+          c1 += c1 < 0 ? n1m : 0;
+          c2 += c2 < 0 ? n2m : 0;
+          const int Rp = (c0 * n1m + c1) * n2m + c2;
+          const Vec16<T> *src = reinterpret_cast<const Vec16<T> *>(Abase + (size_t)Rp * plane + (size_t)ri.x * nbp);
+#pragma unroll
+          for (int v = 0; v < NVEC; ++v) ra[q][v] = src[v];
         }
-        if (nvalid) vb = Cp[tb.row_cp[rr] + n];
+        if (nvalid) {
+          const Vec16<T> *src =
+              reinterpret_cast<const Vec16<T> *>(Bbase + ((long long)(unsigned)ri.z | ((long long)ri.w << 32)));
+#pragma unroll
+          for (int v = 0; v < NVEC; ++v) rb[q][v] = src[v];
+        }
       }
-      ra[e] = va;
-      rb[e] = vb;
     }
   };
   auto store = [&](int buf) {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      As[buf][lr + e][lm] = ra[e];
-      Bs[buf][lr + e][lm] = rb[e];
-    }
+    for (int q = 0; q < RPT; ++q)
+#pragma unroll
+      for (int v = 0; v < NVEC; ++v) {
+        *reinterpret_cast<Vec16<T> *>(&As[buf][rr + 16 * q][8 * c + v * VEC]) = ra[q][v];
+        *reinterpret_cast<Vec16<T> *>(&Bs[buf][rr + 16 * q][8 * c + v * VEC]) = rb[q][v];
+      }
   };
 
   Acc acc[4][4];
@@ -131,15 +174,15 @@ __global__ __launch_bounds__(NS_THREADS) void nstage_kernel(Chi0Tables tb, NTile
         for (int r = 0; r < 4; ++r) acc64[a][b][r] = 0.0;
     }
 
-  const int nk = (S + NS_BK - 1) / NS_BK;
+  const int nk = (S + BK - 1) / BK;
   load(0);
   store(0);
   __syncthreads();
   for (int it = 0; it < nk; ++it) {
     const int cur = it & 1;
-    if (it + 1 < nk) load((it + 1) * NS_BK);
+    if (it + 1 < nk) load((it + 1) * BK);
 #pragma unroll
-    for (int ks = 0; ks < NS_BK / 4; ++ks) {
+    for (int ks = 0; ks < BK / 4; ++ks) {
       T a[4], b[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -172,10 +215,11 @@ __global__ __launch_bounds__(NS_THREADS) void nstage_kernel(Chi0Tables tb, NTile
     for (int r = 0; r < 4; ++r) {
       const int mm = m0 + wm * 64 + tm * 16 + Mfma<T>::row(grp, r);
       if (mm >= M) continue;
-      const int s2 = mm / (nR * nb);
-      const int rem = mm - s2 * nR * nb;
-      const int dR2 = rem / nb;
-      const int k2 = rem - dR2 * nb;
+      const int s2 = mm / (nR * nbp);
+      const int rem = mm - s2 * nR * nbp;
+      const int dR2 = rem / nbp;
+      const int k2 = rem - dR2 * nbp;
+      if (k2 >= nb) continue;
       const int K = tb.atom_of_ao[k2];
       const int kl = k2 - tb.ao_off[K];
       T *dst = Nbuf + tb.noff[((size_t)V * tb.natoms + K) * nR + dR2] + (size_t)(kl * 2 + s2) * NV;
@@ -190,61 +234,94 @@ __global__ __launch_bounds__(NS_THREADS) void nstage_kernel(Chi0Tables tb, NTile
 
 // ---------------------------------------------------------------------------
 // fused M + chi + Z kernel, one workgroup (8 waves) per item (U <= V, R).
-// Wave w owns ABF columns nu in [16w, 16w+16) of V and all mu-tiles of U.
+// Wave w owns ABF columns nu in [16w, 16w+16) of V and all MT mu-tiles of U.
+// Per slice (neighbour K(R1), NAO k of K):
+//   O[i][nu] = sum_j' A[i][j'] N[k][j'][nu]   (JS MFMA K-steps, A = [G^un | G^occ](R) in registers)
+//   chi[mu][nu] += sum_i C[k][i][mu] O[i][nu] (O straight from the accumulator registers)
+// The C slice is staged in LDS mu-major with the i index laid out so that the four
+// contraction rows an accumulator register set covers are adjacent (one 16-byte read);
+// padding rows/columns stay zero.  N rows of the next slice are prefetched into
+// registers, the next C slice through registers into the other LDS buffer.
 // ---------------------------------------------------------------------------
 constexpr int FU_THREADS = 512;
-constexpr int FU_MAXMT = kMaxNaux / 16;     // mu tiles
-constexpr int FU_MAXJS = 2 * kMaxNao / 4;   // K steps of the O GEMM (j' = (s, j))
-constexpr int FU_SLICE = kMaxNao * kMaxNaux;
-constexpr int FU_LOADS = FU_SLICE / FU_THREADS;
+constexpr int FU_MAXNBR = 1024;
+constexpr int FU_LOADS = kMaxNao * kMaxNaux / FU_THREADS;
 
-template <typename T, bool kSplit>
+template <typename T> struct Lds;
+template <> struct Lds<float> {
+  static constexpr int IP = 36;   // padded i extent per mu row (16-byte aligned rows)
+  static __device__ __forceinline__ int slot(int i) { return i; }
+  static __device__ __forceinline__ void read4(const float *p, float c[4]) {
+    const float4 v = *reinterpret_cast<const float4 *>(p);
+    c[0] = v.x; c[1] = v.y; c[2] = v.z; c[3] = v.w;
+  }
+};
+template <> struct Lds<double> {
+  static constexpr int IP = 34;
+  // register r of lane group g covers row g + 4r: place it at slot 4g + r
+  static __device__ __forceinline__ int slot(int i) { return 16 * (i / 16) + 4 * (i % 4) + (i % 16) / 4; }
+  static __device__ __forceinline__ void read4(const double *p, double c[4]) {
+    const double2 a = *reinterpret_cast<const double2 *>(p);
+    const double2 b = *reinterpret_cast<const double2 *>(p + 2);
+    c[0] = a.x; c[1] = a.y; c[2] = b.x; c[3] = b.y;
+  }
+};
+
+template <typename T, bool kSplit, int MT, int JS>
 __global__ __launch_bounds__(FU_THREADS) void fused_kernel(Chi0Tables tb, PairItems items,
-                                                           const T *__restrict__ Gocc,
-                                                           const T *__restrict__ Gun,
+                                                           const T *__restrict__ Gp,
                                                            const T *__restrict__ Cp,
                                                            const T *__restrict__ Nbuf, double negs,
                                                            double *__restrict__ chi) {
   typedef typename Mfma<T>::acc Acc;
-  __shared__ T Cs[2][FU_SLICE];
+  constexpr int IP = Lds<T>::IP;
+  __shared__ __align__(16) T Cs[2][kMaxNaux * IP];
+  __shared__ long long nbr_c[FU_MAXNBR], nbr_n[FU_MAXNBR];
+  __shared__ int nbr_k[FU_MAXNBR];
 
   const int item = blockIdx.x;
   const int U = items.U[item], V = items.V[item], R = items.R[item];
   const int nU = tb.nao[U], aU = tb.naux[U], nV = tb.nao[V], aV = tb.naux[V];
-  const int natoms = tb.natoms, nR = tb.nR, nb = tb.nb;
-  const size_t nbnb = (size_t)nb * nb;
-
+  const int natoms = tb.natoms, nR = tb.nR, nbp = tb.nbp;
+  const size_t plane = (size_t)nbp * nbp;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int col = lane & 15, grp = lane >> 4;
   const int nu = w * 16 + col;
   const bool wave_active = w * 16 < aV;
   const bool nu_ok = nu < aV;
-  const int mt = (aU + 15) / 16;
   const int hc = nU > 16 ? 2 : 1;
-  const int js = (2 * nV + 3) / 4;
+  const int e0 = tb.nbr_start[U], e1 = tb.nbr_start[U + 1];
+  const int ne = e1 - e0;
 
-  // A operand of the O GEMM: A[i][j'] = G^{un}_{ij}(R) for j' = j (pairs with N^occ),
-  //                                     G^{occ}_{ij}(R) for j' = nV + j (pairs with N^un)
-  T afr[2][FU_MAXJS];
+  // neighbour table of this item and zeroed C buffers
+  for (int e = tid; e < ne; e += FU_THREADS) {
+    const int K = tb.nbr_K[e0 + e];
+    nbr_k[e] = tb.nao[K];
+    nbr_c[e] = tb.nbr_cp[e0 + e];
+    nbr_n[e] = tb.noff[((size_t)V * natoms + K) * nR + tb.bvk.sub(tb.nbr_R1[e0 + e], R)];
+  }
+  for (int e = tid; e < 2 * kMaxNaux * IP; e += FU_THREADS) (&Cs[0][0])[e] = T(0);
+
+  // A operand of the O GEMM: A[i][j'] = G^un_ij(R) for j' = j, G^occ_ij(R) for j' = nV + j
+  T afr[2][JS];
 #pragma unroll
   for (int h = 0; h < 2; ++h)
 #pragma unroll
-    for (int st = 0; st < FU_MAXJS; ++st) {
+    for (int st = 0; st < JS; ++st) {
       T v = T(0);
       const int i = 16 * h + col, jp = 4 * st + grp;
-      if (h < hc && st < js && i < nU && jp < 2 * nV) {
-        const int s = jp >= nV;
+      if (h < hc && i < nU && jp < 2 * nV) {
+        const int s = jp >= nV;                  // j' < nV pairs with N^occ and takes G^un
         const int j = jp - s * nV;
-        const T *G = s ? Gocc : Gun;
-        v = G[(size_t)R * nbnb + (size_t)(tb.ao_off[U] + i) * nb + tb.ao_off[V] + j];
+        v = Gp[(size_t)(1 - s) * nR * plane + (size_t)R * plane + (size_t)(tb.ao_off[U] + i) * nbp + tb.ao_off[V] + j];
       }
       afr[h][st] = v;
     }
 
-  Acc acc[FU_MAXMT];
-  double acc64[FU_MAXMT][4];
+  Acc acc[MT];
+  double acc64[MT][4];
 #pragma unroll
-  for (int m = 0; m < FU_MAXMT; ++m) {
+  for (int m = 0; m < MT; ++m) {
     acc[m] = Mfma<T>::zero();
 #pragma unroll
     for (int r = 0; r < 4; ++r) acc64[m][r] = 0.0;
@@ -252,7 +329,7 @@ __global__ __launch_bounds__(FU_THREADS) void fused_kernel(Chi0Tables tb, PairIt
   auto flush = [&]() {
     if (kSplit) {
 #pragma unroll
-      for (int m = 0; m < FU_MAXMT; ++m) {
+      for (int m = 0; m < MT; ++m) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) acc64[m][r] += (double)acc[m][r];
         acc[m] = Mfma<T>::zero();
@@ -279,101 +356,109 @@ __global__ __launch_bounds__(FU_THREADS) void fused_kernel(Chi0Tables tb, PairIt
         }
         const T bz = (fv && nu_ok) ? NB[((size_t)(i * 2 + 1 - s) * nV + j) * aV + nu] : T(0);
 #pragma unroll
-        for (int m = 0; m < FU_MAXMT; ++m) {
-          if (m < mt) {
-            const int mu = 16 * m + col;
-            const T az = (fv && mu < aU) ? NA[((size_t)(j * 2 + s) * nU + i) * aU + mu] : T(0);
-            acc[m] = Mfma<T>::fma(az, bz, acc[m]);
-          }
+        for (int m = 0; m < MT; ++m) {
+          const int mu = 16 * m + col;
+          const T az = (fv && mu < aU) ? NA[((size_t)(j * 2 + s) * nU + i) * aU + mu] : T(0);
+          acc[m] = Mfma<T>::fma(az, bz, acc[m]);
         }
       }
     }
     flush();
   }
+  __syncthreads();   // neighbour table and zeroed buffers visible
 
-  // ---- K(R1) loop over slices k of the packed C blocks [k][i][mu]
-  const int e0 = tb.nbr_start[U], e1 = tb.nbr_start[U + 1];
+  // per-thread LDS destinations of the slice elements (same for every slice of this item);
+  // the 4-slot groups of mu-row mu are XOR-swizzled by (mu / 16) % 4 so that the 64 lanes of
+  // a store hit distinct banks while a register set still reads one aligned 16-byte group
   const int sliceN = nU * aU;
+  const int sliceStride = tb.cp_stride[U];
+  int soff[FU_LOADS];
+#pragma unroll
+  for (int q = 0; q < FU_LOADS; ++q) {
+    const int idx = tid + q * FU_THREADS;
+    soff[q] = -1;
+    if (idx < sliceN) {
+      const int i = idx / aU, mu = idx - i * aU;
+      soff[q] = mu * IP + (Lds<T>::slot(i) ^ (4 * ((mu >> 4) & 3)));
+    }
+  }
   T rc[FU_LOADS];
   auto load_slice = [&](const T *src) {
 #pragma unroll
-    for (int q = 0; q < FU_LOADS; ++q) {
-      const int idx = tid + q * FU_THREADS;
-      rc[q] = idx < sliceN ? src[idx] : T(0);
-    }
+    for (int q = 0; q < FU_LOADS; ++q) rc[q] = soff[q] >= 0 ? src[tid + q * FU_THREADS] : T(0);
   };
   auto store_slice = [&](int buf) {
 #pragma unroll
-    for (int q = 0; q < FU_LOADS; ++q) {
-      const int idx = tid + q * FU_THREADS;
-      if (idx < sliceN) Cs[buf][idx] = rc[q];
+    for (int q = 0; q < FU_LOADS; ++q)
+      if (soff[q] >= 0) Cs[buf][soff[q]] = rc[q];
+  };
+  T nbv[JS], nbn[JS];
+  auto load_n = [&](const T *nrow, T *dst) {
+#pragma unroll
+    for (int st = 0; st < JS; ++st) {
+      const int jp = 4 * st + grp;
+      dst[st] = (jp < 2 * nV && nu_ok) ? nrow[(size_t)jp * aV + nu] : T(0);
     }
   };
 
-  if (e0 < e1) {
-    int e = e0, k = 0, cur = 0;
-    int nK = tb.nao[tb.nbr_K[e]];
-    const T *Cblk = Cp + tb.nbr_cp[e];
-    const T *Nblk = Nbuf + tb.noff[((size_t)V * natoms + tb.nbr_K[e]) * nR + tb.bvk.sub(tb.nbr_R1[e], R)];
+  if (ne > 0) {
+    int e = 0, k = 0, cur = 0;
+    int nK = nbr_k[0];
+    const T *Cblk = Cp + nbr_c[0];
+    const T *Nblk = Nbuf + nbr_n[0];
     load_slice(Cblk);
     store_slice(0);
+    if (wave_active) load_n(Nblk, nbv);
     __syncthreads();
-    while (e < e1) {
+    const size_t nstride = (size_t)2 * nV * aV;
+    while (e < ne) {
       int e2 = e, k2 = k + 1;
       if (k2 == nK) {
         e2 = e + 1;
         k2 = 0;
       }
-      if (e2 < e1) {
-        const T *src = (e2 == e) ? Cblk : (Cp + tb.nbr_cp[e2]);
-        load_slice(src + (size_t)k2 * sliceN);
+      const bool more = e2 < ne;
+      const T *Cnext = Cblk, *Nnext = Nblk;
+      if (more && e2 != e) {
+        Cnext = Cp + nbr_c[e2];
+        Nnext = Nbuf + nbr_n[e2];
+      }
+      if (more) {
+        load_slice(Cnext + (size_t)k2 * sliceStride);
+        if (wave_active) load_n(Nnext + (size_t)k2 * nstride, nbn);
       }
       if (wave_active) {
-        // O[i][nu] = sum_j' A[i][j'] N[k][j'][nu]
         Acc o0 = Mfma<T>::zero(), o1 = Mfma<T>::zero();
-        const T *nrow = Nblk + (size_t)k * 2 * nV * aV;
 #pragma unroll
-        for (int st = 0; st < FU_MAXJS; ++st) {
-          if (st < js) {
-            const int jp = 4 * st + grp;
-            const T b = (jp < 2 * nV && nu_ok) ? nrow[(size_t)jp * aV + nu] : T(0);
-            o0 = Mfma<T>::fma(afr[0][st], b, o0);
-            if (hc > 1) o1 = Mfma<T>::fma(afr[1][st], b, o1);
-          }
+        for (int st = 0; st < JS; ++st) {
+          o0 = Mfma<T>::fma(afr[0][st], nbv[st], o0);
+          if (hc > 1) o1 = Mfma<T>::fma(afr[1][st], nbv[st], o1);
         }
-        // chi[mu][nu] += sum_i C[k][i][mu] O[i][nu]; register r of O holds row i = row(grp, r)
-        const T *cs = Cs[cur];
+        const T *cs = Cs[cur] + col * IP;
 #pragma unroll
-        for (int m = 0; m < FU_MAXMT; ++m) {
-          if (m < mt) {
-            const int mu = 16 * m + col;
-            const bool muok = mu < aU;
+        for (int m = 0; m < MT; ++m) {
+          T c[4];
+          const int g4 = 4 * (grp ^ (m & 3));
+          Lds<T>::read4(cs + 16 * m * IP + g4, c);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              const int i = Mfma<T>::row(grp, r);
-              const T c = (muok && i < nU) ? cs[i * aU + mu] : T(0);
-              acc[m] = Mfma<T>::fma(c, o0[r], acc[m]);
-            }
-            if (hc > 1) {
+          for (int r = 0; r < 4; ++r) acc[m] = Mfma<T>::fma(c[r], o0[r], acc[m]);
+          if (hc > 1) {
+            Lds<T>::read4(cs + 16 * m * IP + 16 + g4, c);
 #pragma unroll
-              for (int r = 0; r < 4; ++r) {
-                const int i = 16 + Mfma<T>::row(grp, r);
-                const T c = (muok && i < nU) ? cs[i * aU + mu] : T(0);
-                acc[m] = Mfma<T>::fma(c, o1[r], acc[m]);
-              }
-            }
+            for (int r = 0; r < 4; ++r) acc[m] = Mfma<T>::fma(c[r], o1[r], acc[m]);
           }
         }
       }
       if (e2 != e) flush();
-      if (e2 < e1) store_slice(cur ^ 1);
+      if (more) store_slice(cur ^ 1);
       __syncthreads();
-      if (e2 != e && e2 < e1) {
-        const int K2 = tb.nbr_K[e2];
-        nK = tb.nao[K2];
-        Cblk = Cp + tb.nbr_cp[e2];
-        Nblk = Nbuf + tb.noff[((size_t)V * natoms + K2) * nR + tb.bvk.sub(tb.nbr_R1[e2], R)];
+      if (more && e2 != e) {
+        nK = nbr_k[e2];
+        Cblk = Cnext;
+        Nblk = Nnext;
       }
+#pragma unroll
+      for (int st = 0; st < JS; ++st) nbv[st] = nbn[st];
       e = e2;
       k = k2;
       cur ^= 1;
@@ -385,16 +470,14 @@ __global__ __launch_bounds__(FU_THREADS) void fused_kernel(Chi0Tables tb, PairIt
   const size_t N = tb.nauxtot;
   const int au0 = tb.aux_off[U], av0 = tb.aux_off[V];
 #pragma unroll
-  for (int m = 0; m < FU_MAXMT; ++m) {
-    if (m < mt) {
+  for (int m = 0; m < MT; ++m) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int mu = 16 * m + Mfma<T>::row(grp, r);
-        if (mu < aU) {
-          const double v = negs * (kSplit ? acc64[m][r] : (double)acc[m][r]);
-          chi[((size_t)R * N + au0 + mu) * N + av0 + nu] = v;
-          if (U != V) chi[((size_t)negR * N + av0 + nu) * N + au0 + mu] = v;
-        }
+    for (int r = 0; r < 4; ++r) {
+      const int mu = 16 * m + Mfma<T>::row(grp, r);
+      if (mu < aU) {
+        const double v = negs * (kSplit ? acc64[m][r] : (double)acc[m][r]);
+        chi[((size_t)R * N + au0 + mu) * N + av0 + nu] = v;
+        if (U != V) chi[((size_t)negR * N + av0 + nu) * N + au0 + mu] = v;
       }
     }
   }
@@ -411,45 +494,92 @@ hipError_t launch_pack_c(const PackTables &pt, const double *C, T *Cp, long long
   return hipGetLastError();
 }
 
-hipError_t launch_convert_g(const double *src, float *dst, size_t n, hipStream_t s) {
+template <typename T>
+hipError_t launch_pad_g(const double *Gocc, const double *Gun, int nR, int nb, int nbp, T *Gp, hipStream_t s) {
+  const size_t n = (size_t)2 * nR * nbp * nbp;
   const int blocks = (int)std::min<size_t>((n + 255) / 256, 65536);
-  hipLaunchKernelGGL(convert_g_kernel, dim3(blocks), dim3(256), 0, s, src, dst, n);
+  hipLaunchKernelGGL(pad_g_kernel<T>, dim3(blocks), dim3(256), 0, s, Gocc, Gun, nR, nb, nbp, Gp);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_nstage(const Chi0Tables &tb, const NTiles &tiles, const T *Gocc, const T *Gun,
-                         const T *Cp, T *Nbuf, hipStream_t s) {
+hipError_t launch_nstage(const Chi0Tables &tb, const NTiles &tiles, const T *Gp, const T *Cp, T *Nbuf,
+                         hipStream_t s) {
   if (tiles.count == 0) return hipSuccess;
   if (sizeof(T) == 4)
-    hipLaunchKernelGGL((nstage_kernel<T, true>), dim3(tiles.count), dim3(NS_THREADS), 0, s, tb, tiles, Gocc,
-                       Gun, Cp, Nbuf);
+    hipLaunchKernelGGL((nstage_kernel<T, true, 32>), dim3(tiles.count), dim3(NS_THREADS), 0, s, tb, tiles, Gp, Cp,
+                       Nbuf);
   else
-    hipLaunchKernelGGL((nstage_kernel<T, false>), dim3(tiles.count), dim3(NS_THREADS), 0, s, tb, tiles, Gocc,
-                       Gun, Cp, Nbuf);
+    hipLaunchKernelGGL((nstage_kernel<T, false, 16>), dim3(tiles.count), dim3(NS_THREADS), 0, s, tb, tiles, Gp, Cp,
+                       Nbuf);
+  return hipGetLastError();
+}
+
+// template classes of the fused kernel: mu-tiles of U and O-GEMM K steps of V
+static const int kMtClass[] = {1, 2, 3, 4, 5, 6, 7, 8};
+static const int kJsClass[] = {2, 4, 7, 10, 13, 16};
+
+int fused_mt_class(int naux) {
+  const int mt = (naux + 15) / 16;
+  for (int c : kMtClass)
+    if (mt <= c) return c;
+  return -1;
+}
+int fused_js_class(int nao) {
+  const int js = (2 * nao + 3) / 4;
+  for (int c : kJsClass)
+    if (js <= c) return c;
+  return -1;
+}
+
+template <typename T, int MT, int JS>
+static void launch_one(const Chi0Tables &tb, const PairItems &items, const T *Gp, const T *Cp, const T *Nbuf,
+                       double negs, double *chi, hipStream_t s) {
+  hipLaunchKernelGGL((fused_kernel<T, sizeof(T) == 4, MT, JS>), dim3(items.count), dim3(FU_THREADS), 0, s, tb,
+                     items, Gp, Cp, Nbuf, negs, chi);
+}
+
+template <typename T, int MT>
+static hipError_t launch_js(int js, const Chi0Tables &tb, const PairItems &items, const T *Gp, const T *Cp,
+                            const T *Nbuf, double negs, double *chi, hipStream_t s) {
+  switch (js) {
+    case 2: launch_one<T, MT, 2>(tb, items, Gp, Cp, Nbuf, negs, chi, s); break;
+    case 4: launch_one<T, MT, 4>(tb, items, Gp, Cp, Nbuf, negs, chi, s); break;
+    case 7: launch_one<T, MT, 7>(tb, items, Gp, Cp, Nbuf, negs, chi, s); break;
+    case 10: launch_one<T, MT, 10>(tb, items, Gp, Cp, Nbuf, negs, chi, s); break;
+    case 13: launch_one<T, MT, 13>(tb, items, Gp, Cp, Nbuf, negs, chi, s); break;
+    case 16: launch_one<T, MT, 16>(tb, items, Gp, Cp, Nbuf, negs, chi, s); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_fused(const Chi0Tables &tb, const PairItems &items, const T *Gocc, const T *Gun,
-                        const T *Cp, const T *Nbuf, double negs, double *chi, hipStream_t s) {
+hipError_t launch_fused(const Chi0Tables &tb, const PairItems &items, int mt, int js, const T *Gp, const T *Cp,
+                        const T *Nbuf, double negs, double *chi, hipStream_t s) {
   if (items.count == 0) return hipSuccess;
-  if (sizeof(T) == 4)
-    hipLaunchKernelGGL((fused_kernel<T, true>), dim3(items.count), dim3(FU_THREADS), 0, s, tb, items, Gocc,
-                       Gun, Cp, Nbuf, negs, chi);
-  else
-    hipLaunchKernelGGL((fused_kernel<T, false>), dim3(items.count), dim3(FU_THREADS), 0, s, tb, items, Gocc,
-                       Gun, Cp, Nbuf, negs, chi);
-  return hipGetLastError();
+  switch (mt) {
+    case 1: return launch_js<T, 1>(js, tb, items, Gp, Cp, Nbuf, negs, chi, s);
+    case 2: return launch_js<T, 2>(js, tb, items, Gp, Cp, Nbuf, negs, chi, s);
+    case 3: return launch_js<T, 3>(js, tb, items, Gp, Cp, Nbuf, negs, chi, s);
+    case 4: return launch_js<T, 4>(js, tb, items, Gp, Cp, Nbuf, negs, chi, s);
+    case 5: return launch_js<T, 5>(js, tb, items, Gp, Cp, Nbuf, negs, chi, s);
+    case 6: return launch_js<T, 6>(js, tb, items, Gp, Cp, Nbuf, negs, chi, s);
+    case 7: return launch_js<T, 7>(js, tb, items, Gp, Cp, Nbuf, negs, chi, s);
+    case 8: return launch_js<T, 8>(js, tb, items, Gp, Cp, Nbuf, negs, chi, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 template hipError_t launch_pack_c<double>(const PackTables &, const double *, double *, long long, hipStream_t);
 template hipError_t launch_pack_c<float>(const PackTables &, const double *, float *, long long, hipStream_t);
+template hipError_t launch_pad_g<double>(const double *, const double *, int, int, int, double *, hipStream_t);
+template hipError_t launch_pad_g<float>(const double *, const double *, int, int, int, float *, hipStream_t);
 template hipError_t launch_nstage<double>(const Chi0Tables &, const NTiles &, const double *, const double *,
-                                          const double *, double *, hipStream_t);
-template hipError_t launch_nstage<float>(const Chi0Tables &, const NTiles &, const float *, const float *,
-                                         const float *, float *, hipStream_t);
-template hipError_t launch_fused<double>(const Chi0Tables &, const PairItems &, const double *, const double *,
+                                          double *, hipStream_t);
+template hipError_t launch_nstage<float>(const Chi0Tables &, const NTiles &, const float *, const float *, float *,
+                                         hipStream_t);
+template hipError_t launch_fused<double>(const Chi0Tables &, const PairItems &, int, int, const double *,
                                          const double *, const double *, double, double *, hipStream_t);
-template hipError_t launch_fused<float>(const Chi0Tables &, const PairItems &, const float *, const float *,
+template hipError_t launch_fused<float>(const Chi0Tables &, const PairItems &, int, int, const float *,
                                         const float *, const float *, double, double *, hipStream_t);
