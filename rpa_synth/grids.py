@@ -29,7 +29,7 @@ def _xs(R, n=2400):
 
 def _tau_init(n, R):
     # 1/x = int_0^inf exp(-x t) dt, t = exp(s): trapezoid in s
-    smin, smax = np.log(0.02 / R), np.log(25.0)
+    smin, smax = np.log(0.02 / R), np.log(20.0)
     s = np.linspace(smin, smax, n)
     h = s[1] - s[0]
     t = np.exp(s)
@@ -47,8 +47,10 @@ def fit_tau(n, R):
         return np.nan_to_num(r, nan=1e6, posinf=1e6, neginf=-1e6)
 
     p0 = np.concatenate([np.log(t0), np.log(w0)])
+    # tau <= 30 / E_min: beyond it exp(-x tau) < 1e-13 for every transition energy, so a point
+    # there would only carry rounding noise
     lo = np.concatenate([np.full(n, np.log(1e-4 / R)), np.full(n, np.log(1e-8 / R))])
-    hi = np.concatenate([np.full(n, np.log(100.0)), np.full(n, np.log(100.0))])
+    hi = np.concatenate([np.full(n, np.log(30.0)), np.full(n, np.log(100.0))])
     sol = least_squares(res, np.clip(p0, lo + 1e-9, hi - 1e-9), bounds=(lo, hi), method="trf",
                         xtol=1e-12, ftol=1e-12, gtol=1e-12, max_nfev=400)
     t, w = np.exp(sol.x[:n]), np.exp(sol.x[n:])
