@@ -392,7 +392,9 @@ __global__ __launch_bounds__(FU_THREADS) void fused_kernel(Chi0Tables tb, PairIt
     for (int q = 0; q < FU_LOADS; ++q)
       if (soff[q] >= 0) Cs[buf][soff[q]] = rc[q];
   };
-  T nbv[JS], nbn[JS];
+  // N rows of the O GEMM, prefetched PF slices ahead (ring of PF + 1 register sets)
+  constexpr int PF = sizeof(T) == 4 ? 2 : 1;
+  T nbr[PF + 1][JS];
   auto load_n = [&](const T *nrow, T *dst) {
 #pragma unroll
     for (int st = 0; st < JS; ++st) {
@@ -400,39 +402,46 @@ __global__ __launch_bounds__(FU_THREADS) void fused_kernel(Chi0Tables tb, PairIt
       dst[st] = (jp < 2 * nV && nu_ok) ? nrow[(size_t)jp * aV + nu] : T(0);
     }
   };
+  const size_t nstride = (size_t)2 * nV * aV;
+  // slice iterator over (neighbour e, NAO k of its K)
+  auto advance = [&](int &ee, int &kk) {
+    if (++kk == nbr_k[ee]) {
+      ++ee;
+      kk = 0;
+    }
+  };
 
   if (ne > 0) {
     int e = 0, k = 0, cur = 0;
-    int nK = nbr_k[0];
-    const T *Cblk = Cp + nbr_c[0];
-    const T *Nblk = Nbuf + nbr_n[0];
-    load_slice(Cblk);
+    load_slice(Cp + nbr_c[0]);
     store_slice(0);
-    if (wave_active) load_n(Nblk, nbv);
+    // prime the N ring with slices 0 .. PF-1
+    {
+      int pe = 0, pk = 0;
+#pragma unroll
+      for (int q = 0; q < PF; ++q) {
+        if (pe < ne && wave_active) load_n(Nbuf + nbr_n[pe] + (size_t)pk * nstride, nbr[q]);
+        if (pe < ne) advance(pe, pk);
+      }
+    }
+    // (pe, pk): the slice PF ahead of (e, k)
+    int pe = 0, pk = 0;
+#pragma unroll
+    for (int q = 0; q < PF; ++q)
+      if (pe < ne) advance(pe, pk);
     __syncthreads();
-    const size_t nstride = (size_t)2 * nV * aV;
     while (e < ne) {
-      int e2 = e, k2 = k + 1;
-      if (k2 == nK) {
-        e2 = e + 1;
-        k2 = 0;
-      }
+      int e2 = e, k2 = k;
+      advance(e2, k2);
       const bool more = e2 < ne;
-      const T *Cnext = Cblk, *Nnext = Nblk;
-      if (more && e2 != e) {
-        Cnext = Cp + nbr_c[e2];
-        Nnext = Nbuf + nbr_n[e2];
-      }
-      if (more) {
-        load_slice(Cnext + (size_t)k2 * sliceStride);
-        if (wave_active) load_n(Nnext + (size_t)k2 * nstride, nbn);
-      }
+      if (more) load_slice(Cp + nbr_c[e2] + (size_t)k2 * sliceStride);
+      if (pe < ne && wave_active) load_n(Nbuf + nbr_n[pe] + (size_t)pk * nstride, nbr[PF]);
       if (wave_active) {
         Acc o0 = Mfma<T>::zero(), o1 = Mfma<T>::zero();
 #pragma unroll
         for (int st = 0; st < JS; ++st) {
-          o0 = Mfma<T>::fma(afr[0][st], nbv[st], o0);
-          if (hc > 1) o1 = Mfma<T>::fma(afr[1][st], nbv[st], o1);
+          o0 = Mfma<T>::fma(afr[0][st], nbr[0][st], o0);
+          if (hc > 1) o1 = Mfma<T>::fma(afr[1][st], nbr[0][st], o1);
         }
         const T *cs = Cs[cur] + col * IP;
 #pragma unroll
@@ -452,13 +461,11 @@ __global__ __launch_bounds__(FU_THREADS) void fused_kernel(Chi0Tables tb, PairIt
       if (e2 != e) flush();
       if (more) store_slice(cur ^ 1);
       __syncthreads();
-      if (more && e2 != e) {
-        nK = nbr_k[e2];
-        Cblk = Cnext;
-        Nblk = Nnext;
-      }
 #pragma unroll
-      for (int st = 0; st < JS; ++st) nbv[st] = nbn[st];
+      for (int q = 0; q < PF; ++q)
+#pragma unroll
+        for (int st = 0; st < JS; ++st) nbr[q][st] = nbr[q + 1][st];
+      if (pe < ne) advance(pe, pk);
       e = e2;
       k = k2;
       cur ^= 1;
