@@ -132,18 +132,19 @@ struct EcLayout {
   size_t L, T, B, W, trB, f, flags, ecq, w, total;
   int cw;
 };
+// L: Cholesky factors of v(q) for every q; T, B: cw (q, omega) matrices at a time
 EcLayout ec_layout(int n, int nq, int nomega, int cw) {
   EcLayout l{};
   const size_t mat = (size_t)n * n * 16;
   size_t o = 0;
   l.L = o;
-  o = align_up(o + mat);
+  o = align_up(o + mat * nq);
   l.T = o;
   o = align_up(o + mat * cw);
   l.B = o;
   o = align_up(o + mat * cw);
   l.W = o;
-  o = align_up(o + (size_t)std::max(cw, 1) * kCholBlock * kCholBlock * 16);
+  o = align_up(o + (size_t)std::max(cw, nq) * kCholBlock * kCholBlock * 16);
   l.trB = o;
   o = align_up(o + (size_t)nq * nomega * 8);
   l.f = o;
@@ -157,6 +158,12 @@ EcLayout ec_layout(int n, int nq, int nomega, int cw) {
   l.total = o;
   l.cw = cw;
   return l;
+}
+// default batch: every (q, omega) pair, capped so that T and B stay within 8 GiB
+int ec_default_batch(int n, int nq, int nomega) {
+  const size_t mat = (size_t)n * n * 16;
+  const size_t cap = std::max<size_t>(1, ((size_t)8 << 30) / (2 * mat));
+  return (int)std::min<size_t>((size_t)nq * nomega, cap);
 }
 }  // namespace
 
@@ -600,7 +607,7 @@ int chi0_R_to_q(rpa_ctx *ctx, const int mesh[3], int nbatch, size_t m, int nq, c
 
 size_t rpa_ec_workspace_size(int n, int nq, int nomega) {
   if (n <= 0 || nq <= 0 || nomega <= 0) return 0;
-  return ec_layout(n, nq, nomega, nomega).total;
+  return ec_layout(n, nq, nomega, ec_default_batch(n, nq, nomega)).total;
 }
 
 int rpa_correlation_energy(rpa_ctx *ctx, int n, int nq, int nomega, const double *womega, const double *chi0_q,
@@ -608,11 +615,13 @@ int rpa_correlation_energy(rpa_ctx *ctx, int n, int nq, int nomega, const double
   if (!ctx) return RPA_ERR_ARG;
   if (!womega || !chi0_q || !v_q || !workspace || !Ec) return fail(ctx, RPA_ERR_ARG, "null pointer");
   if (n <= 0 || nq <= 0 || nomega <= 0) return fail(ctx, RPA_ERR_ARG, "sizes must be positive");
-  int cw = nomega;
-  while (cw > 1 && ec_layout(n, nq, nomega, cw).total > workspace_bytes) --cw;
+  const int total = nq * nomega;
+  int cw = std::min(total, std::max(1, ec_default_batch(n, nq, nomega)));
+  while (cw > 1 && ec_layout(n, nq, nomega, cw).total > workspace_bytes) cw = (cw + 1) / 2;
+  while (cw < total && ec_layout(n, nq, nomega, cw + 1).total <= workspace_bytes) ++cw;
   const EcLayout l = ec_layout(n, nq, nomega, cw);
   if (l.total > workspace_bytes)
-    return fail(ctx, RPA_ERR_WORKSPACE, "workspace smaller than rpa_ec_workspace_size(n, nq, 1)");
+    return fail(ctx, RPA_ERR_WORKSPACE, "workspace smaller than rpa_ec_workspace_size with one matrix per batch");
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   hipStream_t s = ctx->stream;
   char *ws = (char *)workspace;
@@ -624,59 +633,56 @@ int rpa_correlation_energy(rpa_ctx *ctx, int n, int nq, int nomega, const double
   std::unique_ptr<Timed> tm(new Timed(ctx, "ec_stage"));   // closed after the quadrature
   HIP_TRY(ctx, launch_fill_int(flags, (size_t)(nq + nq * nomega), 0, s));
   HIP_TRY(ctx, hipMemcpyAsync(wdev, womega, nomega * 8, hipMemcpyHostToDevice, s));
-  for (int q = 0; q < nq; ++q) {
-    HIP_TRY(ctx, hipMemcpyAsync(L, v_q + q * mat, mat * 8, hipMemcpyDeviceToDevice, s));
-    HIP_TRY(ctx, launch_cholesky(L, mat, n, 1, W, flags, q, s));
-    HIP_TRY(ctx, launch_zero_upper(L, mat, n, 1, s));
-    for (int k0 = 0; k0 < nomega; k0 += cw) {
-      const int nb = std::min(cw, nomega - k0);
-      // T = chi(q, k) L   (L lower triangular: k >= column of the tile)
-      ZgemmArgs g{};
-      g.M = n;
-      g.N = n;
-      g.K = n;
-      g.A = chi0_q + ((size_t)k0 * nq + q) * mat;
-      g.lda = n;
-      g.strideA = (long long)nq * mat;
-      g.opA = 0;
-      g.B = L;
-      g.ldb = n;
-      g.strideB = 0;
-      g.opB = 0;
-      g.C = T;
-      g.ldc = n;
-      g.strideC = mat;
-      g.alpha = 1.0;
-      g.beta = 0.0;
-      g.lower_only = 0;
-      g.kmode = 1;
-      HIP_TRY(ctx, launch_zgemm(g, nb, s));
-      // B = L^H T, lower triangle only (L^H upper triangular: k >= row of the tile)
-      ZgemmArgs h{};
-      h.M = n;
-      h.N = n;
-      h.K = n;
-      h.A = L;
-      h.lda = n;
-      h.strideA = 0;
-      h.opA = 1;
-      h.B = T;
-      h.ldb = n;
-      h.strideB = mat;
-      h.opB = 0;
-      h.C = B;
-      h.ldc = n;
-      h.strideC = mat;
-      h.alpha = 1.0;
-      h.beta = 0.0;
-      h.lower_only = 1;
-      h.kmode = 2;
-      HIP_TRY(ctx, launch_zgemm(h, nb, s));
-      double *trq = trB + (size_t)q * nomega + k0;
-      HIP_TRY(ctx, launch_trace_identity_minus(B, mat, n, nb, trq, s));
-      HIP_TRY(ctx, launch_cholesky(B, mat, n, nb, W, flags, nq + q * nomega + k0, s));
-      HIP_TRY(ctx, launch_logdet(B, mat, n, nb, trq, f + (size_t)q * nomega + k0, flags, nq + q * nomega + k0, s));
-    }
+  // v(q) = L_q L_q^H for every q at once
+  HIP_TRY(ctx, hipMemcpyAsync(L, v_q, nq * mat * 8, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(ctx, launch_cholesky(L, mat, n, nq, W, flags, 0, s));
+  HIP_TRY(ctx, launch_zero_upper(L, mat, n, nq, s));
+  // (q, omega) pairs g = q * nomega + omega in batches of cw
+  for (int b0 = 0; b0 < total; b0 += cw) {
+    const int nb = std::min(cw, total - b0);
+    // T = chi(q, omega) L_q   (L_q lower triangular: k >= first column of the tile)
+    ZgemmArgs g{};
+    g.M = g.N = g.K = n;
+    g.A = chi0_q;
+    g.lda = n;
+    g.outerA = (long long)mat;                 // q
+    g.innerA = (long long)nq * mat;            // omega
+    g.opA = 0;
+    g.B = L;
+    g.ldb = n;
+    g.outerB = (long long)mat;
+    g.opB = 0;
+    g.C = T;
+    g.ldc = n;
+    g.strideC = (long long)mat;
+    g.boff = b0;
+    g.binner = nomega;
+    g.alpha = 1.0;
+    g.kmode = 1;
+    HIP_TRY(ctx, launch_zgemm(g, nb, s));
+    // B = L_q^H T, lower triangle (L^H upper triangular: k >= first row of the tile)
+    ZgemmArgs h{};
+    h.M = h.N = h.K = n;
+    h.A = L;
+    h.lda = n;
+    h.outerA = (long long)mat;
+    h.opA = 1;
+    h.B = T;
+    h.ldb = n;
+    h.strideB = (long long)mat;
+    h.opB = 0;
+    h.C = B;
+    h.ldc = n;
+    h.strideC = (long long)mat;
+    h.boff = b0;
+    h.binner = nomega;
+    h.alpha = 1.0;
+    h.lower_only = 1;
+    h.kmode = 2;
+    HIP_TRY(ctx, launch_zgemm(h, nb, s));
+    HIP_TRY(ctx, launch_trace_identity_minus(B, mat, n, nb, trB + b0, s));
+    HIP_TRY(ctx, launch_cholesky(B, mat, n, nb, W, flags, nq + b0, s));
+    HIP_TRY(ctx, launch_logdet(B, mat, n, nb, trB + b0, f + b0, flags, nq + b0, s));
   }
   HIP_TRY(ctx, launch_quadrature(f, wdev, nq, nomega, ecq, s));
   tm.reset();

@@ -70,7 +70,8 @@ __global__ __launch_bounds__(256) void pad_g_kernel(const double *__restrict__ G
 // Each thread loads, per contraction row, 8 consecutive elements of A and of B with 16-byte
 // vector loads.  128x128 output tile, 4 waves of 64x64 (16x16x4 MFMA), K step BK, LDS
 // double buffer with a padded row stride (conflict-free MFMA operand reads).
-// kSplit: FP32 partial sums are added into FP64 every 256 contraction rows.
+// kSplit (available, not used by the FP32 path): FP32 partial sums added into FP64 every 256
+// contraction rows.
 // ---------------------------------------------------------------------------
 constexpr int NS_BM = 128, NS_BN = 128, NS_THREADS = 256;
 
@@ -514,7 +515,9 @@ hipError_t launch_nstage(const Chi0Tables &tb, const NTiles &tiles, const T *Gp,
                          hipStream_t s) {
   if (tiles.count == 0) return hipSuccess;
   if (sizeof(T) == 4)
-    hipLaunchKernelGGL((nstage_kernel<T, true, 32>), dim3(tiles.count), dim3(NS_THREADS), 0, s, tb, tiles, Gp, Cp,
+    // plain FP32 accumulation over the contraction (about 5000 rows on the 8-atom cell): FP64
+    // side accumulators would cost occupancy for a 5x smaller N error that chi does not need
+    hipLaunchKernelGGL((nstage_kernel<T, false, 32>), dim3(tiles.count), dim3(NS_THREADS), 0, s, tb, tiles, Gp, Cp,
                        Nbuf);
   else
     hipLaunchKernelGGL((nstage_kernel<T, false, 16>), dim3(tiles.count), dim3(NS_THREADS), 0, s, tb, tiles, Gp, Cp,

@@ -3,18 +3,22 @@
 
 #include "common.h"
 
-// C[b] = alpha op(A[b]) op(B[b]) + beta C[b]; complex interleaved, row-major, leading
-// dimensions and batch strides in complex elements / doubles as named.
+// C[l] = alpha op(A[g]) op(B[g]) + beta C[l] for local batch index l = blockIdx.z and global
+// index g = boff + l; complex interleaved, row-major.  Each operand X sits at
+//   X + (g / binner) * outerX + (g % binner) * innerX + l * strideX   (doubles),
+// which covers plain strided batches (outer = inner = 0) and the (q, omega) pairs of the
+// energy stage (q = g / nomega, omega = g % nomega).  Leading dimensions in complex elements.
 struct ZgemmArgs {
   int M, N, K;
   const double *A;
-  long long lda, strideA;   // lda in complex elements, stride in doubles
+  long long lda, strideA, outerA, innerA;
   int opA;                  // 0: A, 1: A^H
   const double *B;
-  long long ldb, strideB;
+  long long ldb, strideB, outerB, innerB;
   int opB;                  // 0: B, 1: B^H
   double *C;
   long long ldc, strideC;
+  int boff, binner;
   double alpha, beta;
   int lower_only;           // skip output tiles strictly above the diagonal
   int kmode;                // 0: all k; 1: k >= first column of the tile (op(B) lower

@@ -15,8 +15,10 @@ __global__ __launch_bounds__(ZT) void zgemm_kernel(ZgemmArgs g) {
   __shared__ double Ar[2][ZK][ZB], Ai[2][ZK][ZB], Br[2][ZK][ZB], Bi[2][ZK][ZB];
   const int n0 = blockIdx.x * ZB, m0 = blockIdx.y * ZB, bz = blockIdx.z;
   if (g.lower_only && n0 > m0 + ZB - 1) return;
-  const double *A = g.A + (size_t)bz * g.strideA;
-  const double *B = g.B + (size_t)bz * g.strideB;
+  const int gb = g.boff + bz, bi = g.binner > 0 ? g.binner : 1;
+  const int go = gb / bi, gi = gb - go * bi;
+  const double *A = g.A + (size_t)bz * g.strideA + (size_t)go * g.outerA + (size_t)gi * g.innerA;
+  const double *B = g.B + (size_t)bz * g.strideB + (size_t)go * g.outerB + (size_t)gi * g.innerB;
   double *C = g.C + (size_t)bz * g.strideC;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = w >> 1, wn = w & 1, col = lane & 15, grp = lane >> 4;
@@ -147,7 +149,7 @@ constexpr int CB = 32;
 
 // Factor the CB x CB diagonal block at (p, p) of matrix blockIdx.x in LDS; write the
 // factor back (lower triangle) and W = (L11^{-1})^H for the panel solve; flag failures.
-__global__ __launch_bounds__(256) void chol_diag_kernel(double *A, size_t stride, int n, int p, double *Wout,
+__global__ __launch_bounds__(64) void chol_diag_kernel(double *A, size_t stride, int n, int p, double *Wout,
                                                         int *flags, int flag_base) {
   __shared__ double2 L[CB][CB + 1];
   __shared__ double2 X[CB][CB + 1];
@@ -350,7 +352,8 @@ hipError_t launch_cholesky(double *A, size_t stride, int n, int batch, double *W
                            hipStream_t s) {
   hipError_t err = hipSuccess;
   for (int p = 0; p < n; p += CB) {
-    hipLaunchKernelGGL(chol_diag_kernel, dim3(batch), dim3(256), 0, s, A, stride, n, p, Wscratch, flags, flag_base);
+    // one wavefront per diagonal block: its barriers are cheap and the block is small
+    hipLaunchKernelGGL(chol_diag_kernel, dim3(batch), dim3(64), 0, s, A, stride, n, p, Wscratch, flags, flag_base);
     if ((err = hipGetLastError()) != hipSuccess) return err;
     const int rest = n - p - CB;
     if (rest <= 0) break;
