@@ -4,6 +4,7 @@
 #include <cmath>
 #include <map>
 #include <memory>
+#include <tuple>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -86,7 +87,7 @@ int drain_profile(rpa_ctx *ctx) {
 }  // namespace
 
 struct PlanGroup {
-  int mt, js, start, count;
+  int mt, js, hc, start, count;
 };
 
 struct rpa_plan {
@@ -103,6 +104,7 @@ struct rpa_plan {
   long long cp_elems = 0, maxblk = 0;
   std::vector<int> nbr_start, nbr_K, nbr_R1;
   std::vector<long long> nbr_cp;
+  std::vector<int> nslices;                     // per atom U: sum of n_K over its neighbours
   std::vector<int> rows_start;
   std::vector<int4> row_info;
   std::vector<long long> noff;
@@ -193,7 +195,7 @@ static int build_impl(rpa_plan *p, const double *G_occ, const double *G_un, cons
     {
       Timed tm(ctx, "fused");
       for (const PlanGroup &g : p->groups)
-        HIP_TRY(ctx, launch_fused<T>(p->tb, p->group_items(g), g.mt, g.js, Gp, Cp, Nb, negs, chi0_tau + t * chistride,
+        HIP_TRY(ctx, launch_fused<T>(p->tb, p->group_items(g), g.mt, g.js, g.hc, Gp, Cp, Nb, negs, chi0_tau + t * chistride,
                                      s));
     }
   }
@@ -339,6 +341,9 @@ int rpa_plan_create(rpa_ctx *ctx, const rpa_cell *cell, const rpa_lri_blocks *bl
     p->nbr_R1[e] = fR[b];
     p->nbr_cp[e] = p->out_off[b];
   }
+  p->nslices.assign(na, 0);
+  for (int a = 0; a < na; ++a)
+    for (int e = p->nbr_start[a]; e < p->nbr_start[a + 1]; ++e) p->nslices[a] += p->nao[p->nbr_K[e]];
   // N-stage contraction rows per atom V
   std::vector<long long> S(na, 0);
   p->rows_start.assign(na + 1, 0);
@@ -381,13 +386,15 @@ int rpa_plan_create(rpa_ctx *ctx, const rpa_cell *cell, const rpa_lri_blocks *bl
   // fused items: atom pairs U <= V (Sec. 3.2 pair set), all R; grouped by the kernel's
   // template classes (mu-tiles of U, O-GEMM steps of V)
   {
-    std::map<std::pair<int, int>, std::vector<std::pair<int, int>>> groups;
+    std::map<std::tuple<int, int, int>, std::vector<std::pair<int, int>>> groups;
     for (int U = 0; U < na; ++U)
-      for (int V = U; V < na; ++V) groups[{fused_mt_class(p->naux[U]), fused_js_class(p->nao[V])}].push_back({U, V});
+      for (int V = U; V < na; ++V)
+        groups[{fused_mt_class(p->naux[U]), fused_js_class(p->nao[V]), p->nao[U] > 16 ? 2 : 1}].push_back({U, V});
     for (auto &g : groups) {
       PlanGroup pg;
-      pg.mt = g.first.first;
-      pg.js = g.first.second;
+      pg.mt = std::get<0>(g.first);
+      pg.js = std::get<1>(g.first);
+      pg.hc = std::get<2>(g.first);
       pg.start = (int)p->itemU.size();
       for (auto &uv : g.second)
         for (int r = 0; r < nR; ++r) {
@@ -449,7 +456,7 @@ int rpa_plan_create(rpa_ctx *ctx, const rpa_cell *cell, const rpa_lri_blocks *bl
                s_pin = add(p->in_off.data(), nblk * 8), s_pout = add(p->out_off.data(), nblk * 8),
                s_pa = add(p->blk_a.data(), nblk * 4), s_pni = add(p->blk_ni.data(), nblk * 4),
                s_pnk = add(p->blk_nk.data(), nblk * 4), s_pst = add(p->blk_stride.data(), nblk * 4),
-               s_cst = add(p->cp_stride.data(), na * 4);
+               s_cst = add(p->cp_stride.data(), na * 4), s_nsl = add(p->nslices.data(), na * 4);
   hipError_t he = hipSetDevice(ctx->device);
   if (he == hipSuccess) he = hipMalloc(&p->dtab, tot);
   if (he != hipSuccess) {
@@ -482,6 +489,7 @@ int rpa_plan_create(rpa_ctx *ctx, const rpa_cell *cell, const rpa_lri_blocks *bl
   tb.row_info = (const int4 *)(d + secs[s_ri].off);
   tb.noff = I64(s_noff);
   tb.cp_stride = I32(s_cst);
+  tb.nslices = I32(s_nsl);
   tb.natoms = na;
   tb.nb = p->nb;
   tb.nbp = p->nbp;

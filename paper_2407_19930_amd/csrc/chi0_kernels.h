@@ -12,6 +12,7 @@ struct Chi0Tables {
   const int *nbr_start;                       // [natoms + 1]
   const int *nbr_K, *nbr_R1;                  // [nblk] second atom, folded lattice vector
   const long long *nbr_cp;                    // [nblk] offset of the packed block [k][i][mu]
+  const int *nslices;                         // [natoms] sum of nao[K] over the neighbours of U
   // contraction rows of the N-stage for atom V: r in [rows_start[V], rows_start[V+1])
   //   row r <-> (neighbour L(dL) of V, NAO l of L); row_info[r] = {G row ao_off[L] + l,
   //   BvK components of dL packed as d0 | d1 << 10 | d2 << 20, packed-C offset of row
@@ -50,12 +51,12 @@ template <typename T>
 hipError_t launch_nstage(const Chi0Tables &tb, const NTiles &tiles, const T *Gp, const T *Cp, T *Nbuf,
                          hipStream_t s);
 // Fused kernel for a group of items whose atoms share the template classes
-// mt = fused_mt_class(naux_U) and js = fused_js_class(nao_V).
+// mt = fused_mt_class(naux_U), js = fused_js_class(nao_V) and hc = i-tiles of U (1 or 2).
 int fused_mt_class(int naux);
 int fused_js_class(int nao);
 template <typename T>
-hipError_t launch_fused(const Chi0Tables &tb, const PairItems &items, int mt, int js, const T *Gp, const T *Cp,
-                        const T *Nbuf, double negs, double *chi, hipStream_t s);
+hipError_t launch_fused(const Chi0Tables &tb, const PairItems &items, int mt, int js, int hc, const T *Gp,
+                        const T *Cp, const T *Nbuf, double negs, double *chi, hipStream_t s);
 
 // compile-time limits of the kernels
 constexpr int kMaxNao = 32;     // NAOs per atom

@@ -268,7 +268,27 @@ template <> struct Lds<double> {
   }
 };
 
-template <typename T, bool kSplit, int MT, int JS>
+// wave-uniform copies of values every lane holds alike (loop state from LDS tables)
+__device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ long long uniform(long long x) {
+  const unsigned lo = __builtin_amdgcn_readfirstlane((int)(x & 0xffffffffll));
+  const unsigned hi = __builtin_amdgcn_readfirstlane((int)(x >> 32));
+  return (long long)(((unsigned long long)hi << 32) | lo);
+}
+// raw buffer view of [p, p + nbytes): loads at byte offsets >= nbytes return zero without a
+// memory access, so the masked loads of the slice loop need no branches
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_view(const void *p, unsigned nbytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)nbytes, 0x00020000);
+}
+template <typename T> __device__ __forceinline__ T buffer_load(__amdgpu_buffer_rsrc_t r, unsigned off);
+template <> __device__ __forceinline__ float buffer_load<float>(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+template <> __device__ __forceinline__ double buffer_load<double>(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+
+template <typename T, bool kSplit, int MT, int JS, int HC>
 __global__ __launch_bounds__(FU_THREADS) void fused_kernel(Chi0Tables tb, PairItems items,
                                                            const T *__restrict__ Gp,
                                                            const T *__restrict__ Cp,
@@ -276,7 +296,9 @@ __global__ __launch_bounds__(FU_THREADS) void fused_kernel(Chi0Tables tb, PairIt
                                                            double *__restrict__ chi) {
   typedef typename Mfma<T>::acc Acc;
   constexpr int IP = Lds<T>::IP;
-  __shared__ __align__(16) T Cs[2][kMaxNaux * IP];
+  constexpr int CG = sizeof(T) == 4 ? 4 : 1;    // mu-tiles per group of C fragment reads
+  // two C slice buffers; the element after them takes the stores of idle threads
+  __shared__ __align__(16) T Cs[2 * kMaxNaux * IP + 4];
   __shared__ long long nbr_c[FU_MAXNBR], nbr_n[FU_MAXNBR];
   __shared__ int nbr_k[FU_MAXNBR];
 
@@ -285,12 +307,12 @@ __global__ __launch_bounds__(FU_THREADS) void fused_kernel(Chi0Tables tb, PairIt
   const int nU = tb.nao[U], aU = tb.naux[U], nV = tb.nao[V], aV = tb.naux[V];
   const int natoms = tb.natoms, nR = tb.nR, nbp = tb.nbp;
   const size_t plane = (size_t)nbp * nbp;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, w = uniform(tid >> 6);
   const int col = lane & 15, grp = lane >> 4;
   const int nu = w * 16 + col;
   const bool wave_active = w * 16 < aV;
   const bool nu_ok = nu < aV;
-  const int hc = nU > 16 ? 2 : 1;
+  const int hc = HC;                          // i-tiles of U (nU <= 16 HC)
   const int e0 = tb.nbr_start[U], e1 = tb.nbr_start[U + 1];
   const int ne = e1 - e0;
 
@@ -301,12 +323,12 @@ __global__ __launch_bounds__(FU_THREADS) void fused_kernel(Chi0Tables tb, PairIt
     nbr_c[e] = tb.nbr_cp[e0 + e];
     nbr_n[e] = tb.noff[((size_t)V * natoms + K) * nR + tb.bvk.sub(tb.nbr_R1[e0 + e], R)];
   }
-  for (int e = tid; e < 2 * kMaxNaux * IP; e += FU_THREADS) (&Cs[0][0])[e] = T(0);
+  for (int e = tid; e < 2 * kMaxNaux * IP + 4; e += FU_THREADS) Cs[e] = T(0);
 
   // A operand of the O GEMM: A[i][j'] = G^un_ij(R) for j' = j, G^occ_ij(R) for j' = nV + j
-  T afr[2][JS];
+  T afr[HC][JS];
 #pragma unroll
-  for (int h = 0; h < 2; ++h)
+  for (int h = 0; h < HC; ++h)
 #pragma unroll
     for (int st = 0; st < JS; ++st) {
       T v = T(0);
@@ -370,14 +392,16 @@ __global__ __launch_bounds__(FU_THREADS) void fused_kernel(Chi0Tables tb, PairIt
 
   // per-thread LDS destinations of the slice elements (same for every slice of this item);
   // the 4-slot groups of mu-row mu are XOR-swizzled by (mu / 16) % 4 so that the 64 lanes of
-  // a store hit distinct banks while a register set still reads one aligned 16-byte group
+  // a store hit distinct banks while a register set still reads one aligned 16-byte group.
+  // Threads past the slice store to the spare element.
   const int sliceN = nU * aU;
   const int sliceStride = tb.cp_stride[U];
+  constexpr int kSpare = 2 * kMaxNaux * IP;
   int soff[FU_LOADS];
 #pragma unroll
   for (int q = 0; q < FU_LOADS; ++q) {
     const int idx = tid + q * FU_THREADS;
-    soff[q] = -1;
+    soff[q] = kSpare;
     if (idx < sliceN) {
       const int i = idx / aU, mu = idx - i * aU;
       soff[q] = mu * IP + (Lds<T>::slot(i) ^ (4 * ((mu >> 4) & 3)));
@@ -385,91 +409,93 @@ __global__ __launch_bounds__(FU_THREADS) void fused_kernel(Chi0Tables tb, PairIt
   }
   T rc[FU_LOADS];
   auto load_slice = [&](const T *src) {
+    const __amdgpu_buffer_rsrc_t r = buffer_view(src, (unsigned)(sliceN * sizeof(T)));
 #pragma unroll
-    for (int q = 0; q < FU_LOADS; ++q) rc[q] = soff[q] >= 0 ? src[tid + q * FU_THREADS] : T(0);
+    for (int q = 0; q < FU_LOADS; ++q) rc[q] = buffer_load<T>(r, (unsigned)((tid + q * FU_THREADS) * sizeof(T)));
   };
   auto store_slice = [&](int buf) {
+    T *dst = Cs + buf * (kMaxNaux * IP);
 #pragma unroll
-    for (int q = 0; q < FU_LOADS; ++q)
-      if (soff[q] >= 0) Cs[buf][soff[q]] = rc[q];
+    for (int q = 0; q < FU_LOADS; ++q) (soff[q] == kSpare ? Cs : dst)[soff[q]] = rc[q];
   };
-  // N rows of the O GEMM, prefetched PF slices ahead (ring of PF + 1 register sets)
-  constexpr int PF = sizeof(T) == 4 ? 2 : 1;
-  T nbr[PF + 1][JS];
-  auto load_n = [&](const T *nrow, T *dst) {
-#pragma unroll
-    for (int st = 0; st < JS; ++st) {
-      const int jp = 4 * st + grp;
-      dst[st] = (jp < 2 * nV && nu_ok) ? nrow[(size_t)jp * aV + nu] : T(0);
-    }
-  };
+  // N rows of the O GEMM: two register sets used in turn (the loop body is unrolled twice so
+  // that no register copy forces a wait on the loads just issued for the next slice).  Rows
+  // j' >= 2 nV read zero (their A columns are zero too); columns nu >= aV are never stored.
   const size_t nstride = (size_t)2 * nV * aV;
-  // slice iterator over (neighbour e, NAO k of its K)
-  auto advance = [&](int &ee, int &kk) {
-    if (++kk == nbr_k[ee]) {
-      ++ee;
-      kk = 0;
+  T nbA[JS], nbB[JS];
+  // (idle waves get an empty view: their loads return zero without a memory access, and the
+  // loads stay unconditional so that the wait counts after them are exact)
+  const unsigned nview = wave_active ? (unsigned)(nstride * sizeof(T)) : 0u;
+  auto load_n = [&](const T *nrow, T *dst) {
+    const __amdgpu_buffer_rsrc_t r = buffer_view(nrow, nview);
+#pragma unroll
+    for (int st = 0; st < JS; ++st) dst[st] = buffer_load<T>(r, (unsigned)(((4 * st + grp) * aV + nu) * sizeof(T)));
+  };
+  int e = 0, k = 0, cur = 0;
+  // one slice: prefetch C and N of the next slice (slice (0, 0) again after the last),
+  // O GEMM, chi += C O, stage the next C slice, barrier.  The loop runs over pairs of slices;
+  // the second slice of the last pair may be past the end, and then only its GEMMs are
+  // skipped: loads, stores and barriers run on every path so that the wait counts the
+  // compiler derives are exact and the prefetch stays in flight across the barrier.
+  auto slice = [&](const T *nbcur, T *nbnext, bool live) __attribute__((always_inline)) {
+    int e2 = e, k2 = k;
+    if (live) {
+      k2 = k + 1;
+      if (k2 == uniform(nbr_k[e])) {
+        e2 = e + 1;
+        k2 = 0;
+      }
     }
+    // past the last slice the loads go to slice (0, 0), which every item has (ne > 0)
+    const bool more = e2 < ne;
+    const int ea = more ? e2 : 0, ka = more ? k2 : 0;
+    load_slice(Cp + uniform(nbr_c[ea]) + (size_t)ka * sliceStride);
+    load_n(Nbuf + uniform(nbr_n[ea]) + (size_t)ka * nstride, nbnext);
+    // keep the prefetch ahead of the GEMMs (the scheduler would otherwise sink it to shorten
+    // register lifetimes, and the next slice would wait for it)
+    __builtin_amdgcn_sched_barrier(0);
+    if (live && wave_active) {
+      Acc o[HC];
+#pragma unroll
+      for (int h = 0; h < HC; ++h) o[h] = Mfma<T>::zero();
+#pragma unroll
+      for (int st = 0; st < JS; ++st)
+#pragma unroll
+        for (int h = 0; h < HC; ++h) o[h] = Mfma<T>::fma(afr[h][st], nbcur[st], o[h]);
+      const T *cs = Cs + cur * (kMaxNaux * IP) + col * IP;
+      // C fragments of CG mu-tiles are read first, then their MFMAs issued round-robin over
+      // the tiles so that consecutive MFMAs never wait on each other's accumulator
+#pragma unroll
+      for (int h = 0; h < HC; ++h)
+#pragma unroll
+        for (int m0 = 0; m0 < MT; m0 += CG) {
+          T c[CG][4];
+#pragma unroll
+          for (int m = m0; m < m0 + CG && m < MT; ++m)
+            Lds<T>::read4(cs + 16 * m * IP + 16 * h + 4 * (grp ^ (m & 3)), c[m - m0]);
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int m = m0; m < m0 + CG && m < MT; ++m) acc[m] = Mfma<T>::fma(c[m - m0][r], o[h][r], acc[m]);
+        }
+    }
+    if (e2 != e) flush();
+    store_slice(cur ^ 1);
+    __syncthreads();
+    e = e2;
+    k = k2;
+    cur ^= 1;
   };
 
+  const int nsl = tb.nslices[U];
   if (ne > 0) {
-    int e = 0, k = 0, cur = 0;
-    load_slice(Cp + nbr_c[0]);
+    load_slice(Cp + uniform(nbr_c[0]));
     store_slice(0);
-    // prime the N ring with slices 0 .. PF-1
-    {
-      int pe = 0, pk = 0;
-#pragma unroll
-      for (int q = 0; q < PF; ++q) {
-        if (pe < ne && wave_active) load_n(Nbuf + nbr_n[pe] + (size_t)pk * nstride, nbr[q]);
-        if (pe < ne) advance(pe, pk);
-      }
-    }
-    // (pe, pk): the slice PF ahead of (e, k)
-    int pe = 0, pk = 0;
-#pragma unroll
-    for (int q = 0; q < PF; ++q)
-      if (pe < ne) advance(pe, pk);
+    load_n(Nbuf + uniform(nbr_n[0]), nbA);
     __syncthreads();
-    while (e < ne) {
-      int e2 = e, k2 = k;
-      advance(e2, k2);
-      const bool more = e2 < ne;
-      if (more) load_slice(Cp + nbr_c[e2] + (size_t)k2 * sliceStride);
-      if (pe < ne && wave_active) load_n(Nbuf + nbr_n[pe] + (size_t)pk * nstride, nbr[PF]);
-      if (wave_active) {
-        Acc o0 = Mfma<T>::zero(), o1 = Mfma<T>::zero();
-#pragma unroll
-        for (int st = 0; st < JS; ++st) {
-          o0 = Mfma<T>::fma(afr[0][st], nbr[0][st], o0);
-          if (hc > 1) o1 = Mfma<T>::fma(afr[1][st], nbr[0][st], o1);
-        }
-        const T *cs = Cs[cur] + col * IP;
-#pragma unroll
-        for (int m = 0; m < MT; ++m) {
-          T c[4];
-          const int g4 = 4 * (grp ^ (m & 3));
-          Lds<T>::read4(cs + 16 * m * IP + g4, c);
-#pragma unroll
-          for (int r = 0; r < 4; ++r) acc[m] = Mfma<T>::fma(c[r], o0[r], acc[m]);
-          if (hc > 1) {
-            Lds<T>::read4(cs + 16 * m * IP + 16 + g4, c);
-#pragma unroll
-            for (int r = 0; r < 4; ++r) acc[m] = Mfma<T>::fma(c[r], o1[r], acc[m]);
-          }
-        }
-      }
-      if (e2 != e) flush();
-      if (more) store_slice(cur ^ 1);
-      __syncthreads();
-#pragma unroll
-      for (int q = 0; q < PF; ++q)
-#pragma unroll
-        for (int st = 0; st < JS; ++st) nbr[q][st] = nbr[q + 1][st];
-      if (pe < ne) advance(pe, pk);
-      e = e2;
-      k = k2;
-      cur ^= 1;
+    for (int t = 0; t < nsl; t += 2) {
+      slice(nbA, nbB, true);
+      slice(nbB, nbA, t + 1 < nsl);
     }
   }
 
@@ -543,40 +569,44 @@ int fused_js_class(int nao) {
 }
 
 template <typename T, int MT, int JS>
-static void launch_one(const Chi0Tables &tb, const PairItems &items, const T *Gp, const T *Cp, const T *Nbuf,
-                       double negs, double *chi, hipStream_t s) {
-  hipLaunchKernelGGL((fused_kernel<T, sizeof(T) == 4, MT, JS>), dim3(items.count), dim3(FU_THREADS), 0, s, tb,
-                     items, Gp, Cp, Nbuf, negs, chi);
+static void launch_one(int hc, const Chi0Tables &tb, const PairItems &items, const T *Gp, const T *Cp,
+                       const T *Nbuf, double negs, double *chi, hipStream_t s) {
+  if (hc == 1)
+    hipLaunchKernelGGL((fused_kernel<T, sizeof(T) == 4, MT, JS, 1>), dim3(items.count), dim3(FU_THREADS), 0, s, tb,
+                       items, Gp, Cp, Nbuf, negs, chi);
+  else
+    hipLaunchKernelGGL((fused_kernel<T, sizeof(T) == 4, MT, JS, 2>), dim3(items.count), dim3(FU_THREADS), 0, s, tb,
+                       items, Gp, Cp, Nbuf, negs, chi);
 }
 
 template <typename T, int MT>
-static hipError_t launch_js(int js, const Chi0Tables &tb, const PairItems &items, const T *Gp, const T *Cp,
+static hipError_t launch_js(int js, int hc, const Chi0Tables &tb, const PairItems &items, const T *Gp, const T *Cp,
                             const T *Nbuf, double negs, double *chi, hipStream_t s) {
   switch (js) {
-    case 2: launch_one<T, MT, 2>(tb, items, Gp, Cp, Nbuf, negs, chi, s); break;
-    case 4: launch_one<T, MT, 4>(tb, items, Gp, Cp, Nbuf, negs, chi, s); break;
-    case 7: launch_one<T, MT, 7>(tb, items, Gp, Cp, Nbuf, negs, chi, s); break;
-    case 10: launch_one<T, MT, 10>(tb, items, Gp, Cp, Nbuf, negs, chi, s); break;
-    case 13: launch_one<T, MT, 13>(tb, items, Gp, Cp, Nbuf, negs, chi, s); break;
-    case 16: launch_one<T, MT, 16>(tb, items, Gp, Cp, Nbuf, negs, chi, s); break;
+    case 2: launch_one<T, MT, 2>(hc, tb, items, Gp, Cp, Nbuf, negs, chi, s); break;
+    case 4: launch_one<T, MT, 4>(hc, tb, items, Gp, Cp, Nbuf, negs, chi, s); break;
+    case 7: launch_one<T, MT, 7>(hc, tb, items, Gp, Cp, Nbuf, negs, chi, s); break;
+    case 10: launch_one<T, MT, 10>(hc, tb, items, Gp, Cp, Nbuf, negs, chi, s); break;
+    case 13: launch_one<T, MT, 13>(hc, tb, items, Gp, Cp, Nbuf, negs, chi, s); break;
+    case 16: launch_one<T, MT, 16>(hc, tb, items, Gp, Cp, Nbuf, negs, chi, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_fused(const Chi0Tables &tb, const PairItems &items, int mt, int js, const T *Gp, const T *Cp,
-                        const T *Nbuf, double negs, double *chi, hipStream_t s) {
+hipError_t launch_fused(const Chi0Tables &tb, const PairItems &items, int mt, int js, int hc, const T *Gp,
+                        const T *Cp, const T *Nbuf, double negs, double *chi, hipStream_t s) {
   if (items.count == 0) return hipSuccess;
   switch (mt) {
-    case 1: return launch_js<T, 1>(js, tb, items, Gp, Cp, Nbuf, negs, chi, s);
-    case 2: return launch_js<T, 2>(js, tb, items, Gp, Cp, Nbuf, negs, chi, s);
-    case 3: return launch_js<T, 3>(js, tb, items, Gp, Cp, Nbuf, negs, chi, s);
-    case 4: return launch_js<T, 4>(js, tb, items, Gp, Cp, Nbuf, negs, chi, s);
-    case 5: return launch_js<T, 5>(js, tb, items, Gp, Cp, Nbuf, negs, chi, s);
-    case 6: return launch_js<T, 6>(js, tb, items, Gp, Cp, Nbuf, negs, chi, s);
-    case 7: return launch_js<T, 7>(js, tb, items, Gp, Cp, Nbuf, negs, chi, s);
-    case 8: return launch_js<T, 8>(js, tb, items, Gp, Cp, Nbuf, negs, chi, s);
+    case 1: return launch_js<T, 1>(js, hc, tb, items, Gp, Cp, Nbuf, negs, chi, s);
+    case 2: return launch_js<T, 2>(js, hc, tb, items, Gp, Cp, Nbuf, negs, chi, s);
+    case 3: return launch_js<T, 3>(js, hc, tb, items, Gp, Cp, Nbuf, negs, chi, s);
+    case 4: return launch_js<T, 4>(js, hc, tb, items, Gp, Cp, Nbuf, negs, chi, s);
+    case 5: return launch_js<T, 5>(js, hc, tb, items, Gp, Cp, Nbuf, negs, chi, s);
+    case 6: return launch_js<T, 6>(js, hc, tb, items, Gp, Cp, Nbuf, negs, chi, s);
+    case 7: return launch_js<T, 7>(js, hc, tb, items, Gp, Cp, Nbuf, negs, chi, s);
+    case 8: return launch_js<T, 8>(js, hc, tb, items, Gp, Cp, Nbuf, negs, chi, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -589,7 +619,7 @@ template hipError_t launch_nstage<double>(const Chi0Tables &, const NTiles &, co
                                           double *, hipStream_t);
 template hipError_t launch_nstage<float>(const Chi0Tables &, const NTiles &, const float *, const float *, float *,
                                          hipStream_t);
-template hipError_t launch_fused<double>(const Chi0Tables &, const PairItems &, int, int, const double *,
+template hipError_t launch_fused<double>(const Chi0Tables &, const PairItems &, int, int, int, const double *,
                                          const double *, const double *, double, double *, hipStream_t);
-template hipError_t launch_fused<float>(const Chi0Tables &, const PairItems &, int, int, const float *,
+template hipError_t launch_fused<float>(const Chi0Tables &, const PairItems &, int, int, int, const float *,
                                         const float *, const float *, double, double *, hipStream_t);
