@@ -26,6 +26,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
+# sources of the chi0 kernels; the HBM traffic recorded under profiles/ is used only while
+# their hash matches the one the counters were taken with
+KERNEL_SOURCES = ("paper_2407_19930_amd/csrc/chi0_kernels.hip", "paper_2407_19930_amd/csrc/chi0_kernels.h",
+                  "paper_2407_19930_amd/csrc/common.h")
 
 
 def log(*a):
@@ -42,7 +46,34 @@ def parse():
     ap.add_argument("--no-fp64-check", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run a plain 1 GiB device copy first (reference dispatch for the byte counters)")
     return ap.parse_args()
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(kernel, precision, workload):
+    """HBM bytes per launch from the committed counter summary, or None when there is none for
+    this kernel/precision/workload or the kernel sources changed since it was taken.  The
+    summary holds lines `traffic <kernel> <precision> <workload> <bytes per launch> <hash>`."""
+    path = os.path.join(ROOT, "profiles", "pmc_%s_%s_%s.md" % (kernel, workload, precision))
+    if not os.path.exists(path):
+        return None
+    cur = kernel_source_hash()
+    with open(path) as fh:
+        for line in fh:
+            f = line.strip().strip("`").split()
+            if len(f) == 6 and f[0] == "traffic" and f[1:4] == [kernel, precision, workload]:
+                return float(f[4]) if f[5] == cur else None
+    return None
 
 
 def cpu_baseline(inp, budget_s):
@@ -105,6 +136,14 @@ def main():
     ws_ec = torch.empty(rpa_ec_workspace_size(N, nq, nw), dtype=torch.uint8, device=dev)
     ctx = Context(0)
     b = inp.blocks
+    if args.calibrate_copy:
+        # 2^28 floats: 1 GiB read and 1 GiB written by one copy kernel
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("calibration copy done (1 GiB read, 1 GiB written)")
 
     def make_plan(prec):
         p = Plan(ctx, inp.nao, inp.naux, cell.mesh, b.I, b.K, b.R, b.off, nt, prec)
@@ -156,7 +195,7 @@ def main():
     achieved = per_launch / (avg_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[args.precision]
     roofline = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                "traffic": None, "kernel": dom,
+                "traffic": recorded_traffic(dom, args.precision, cell.name), "kernel": dom,
                 "executed_tflops": st_exec / nt / (avg_ms * 1e-3) / 1e12}
 
     if not args.no_fp64_check and args.precision != "fp64":
