@@ -52,9 +52,15 @@ typedef enum {
   RPA_ERR_UNSUPPORTED = 7   /* shape outside the compiled kernel limits */
 } rpa_status;
 
+/* Arithmetic of the chi0 build.  G is always passed in FP64; the FP32 and BF16X3
+ * paths scale G^occ and G^un of each tau by powers of two (max abs in [1, 2)) before
+ * the cast and remove the scale in FP64 when writing chi. */
 typedef enum {
   RPA_FP64 = 0,             /* every contraction in FP64 (MFMA f64) */
-  RPA_FP32 = 1              /* contractions in FP32 (MFMA f32), FP64 across neighbour blocks */
+  RPA_FP32 = 1,             /* contractions in FP32 (MFMA f32), FP64 across neighbour blocks */
+  RPA_BF16X3 = 2            /* N stage as RPA_FP32; the neighbour loop (O and chi += C O) in
+                               split BF16: x = hi + lo, a b = a_hi b_hi + a_hi b_lo + a_lo b_hi
+                               on the bf16 MFMAs, FP32 accumulation, FP64 across neighbour blocks */
 } rpa_precision;
 
 typedef struct rpa_ctx rpa_ctx;

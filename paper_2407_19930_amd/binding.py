@@ -17,8 +17,8 @@ LIB_PATH = os.path.join(HERE, "librpa_mi355x.so")
 
 RPA_OK, RPA_ERR_ARG, RPA_ERR_SHAPE, RPA_ERR_WORKSPACE, RPA_ERR_NOT_HPD, RPA_ERR_NONFINITE, RPA_ERR_HIP, \
     RPA_ERR_UNSUPPORTED = range(8)
-RPA_FP64, RPA_FP32 = 0, 1
-PRECISIONS = {"fp64": RPA_FP64, "fp32": RPA_FP32}
+RPA_FP64, RPA_FP32, RPA_BF16X3 = 0, 1, 2
+PRECISIONS = {"fp64": RPA_FP64, "fp32": RPA_FP32, "bf16x3": RPA_BF16X3}
 
 EXPORTED = ["rpa_create", "rpa_set_stream", "rpa_destroy", "rpa_last_error", "rpa_plan_create",
             "rpa_plan_destroy", "rpa_plan_flops", "rpa_plan_stage_flops", "rpa_profile", "rpa_profile_read",

@@ -98,12 +98,14 @@ struct rpa_plan {
   Bvk bvk{1, 1, 1};
   std::vector<int> nao, naux, ao_off, aux_off, atom_of_ao;
   std::vector<long long> in_off, out_off;      // caller block offsets, packed offsets
+  std::vector<long long> cb_off;                // split-BF16 packed offsets (bf16 elements)
+  long long cb_elems = 0;
   std::vector<int> blk_a, blk_ni, blk_nk, blk_stride;
   std::vector<int> cp_stride;                   // per atom: packed row length, nao*naux rounded up to 8
   int nbp = 0;                                  // nb rounded up to 8
   long long cp_elems = 0, maxblk = 0;
   std::vector<int> nbr_start, nbr_K, nbr_R1;
-  std::vector<long long> nbr_cp;
+  std::vector<long long> nbr_cp, nbr_cb;
   std::vector<int> nslices;                     // per atom U: sum of n_K over its neighbours
   std::vector<int> rows_start;
   std::vector<int4> row_info;
@@ -121,7 +123,7 @@ struct rpa_plan {
   PairItems items{};
   PackTables pack{};
   // workspace layout (bytes)
-  size_t ws_cp = 0, ws_g = 0, ws_n = 0, ws_total = 0;
+  size_t ws_cp = 0, ws_cb = 0, ws_g = 0, ws_n = 0, ws_sc = 0, ws_total = 0;
 
   PairItems group_items(const PlanGroup &g) const {
     return PairItems{items.U + g.start, items.V + g.start, items.R + g.start, g.count};
@@ -169,24 +171,31 @@ int ec_default_batch(int n, int nq, int nomega) {
 }
 }  // namespace
 
+// T: precision of G, N and the N stage; bf16: split-BF16 fused kernel (T = float).  G is rescaled
+// per tau by a power of two in the FP32 and BF16X3 paths.
 template <typename T>
 static int build_impl(rpa_plan *p, const double *G_occ, const double *G_un, const double *C, char *ws, double negs,
-                      double *chi0_tau) {
+                      double *chi0_tau, bool bf16) {
   rpa_ctx *ctx = p->ctx;
   hipStream_t s = ctx->stream;
   const size_t gstride = (size_t)p->nR * p->nb * p->nb;
   const size_t chistride = (size_t)p->nR * p->nauxtot * p->nauxtot;
   T *Cp = (T *)(ws + p->ws_cp);
+  uint16_t *Cb = (uint16_t *)(ws + p->ws_cb);
   T *Gp = (T *)(ws + p->ws_g);
   T *Nb = (T *)(ws + p->ws_n);
+  double *gpart = (double *)(ws + p->ws_sc);
+  int *gexp = sizeof(T) == 4 ? (int *)(gpart + 2 * kGscaleBlocks) : nullptr;
   {
     Timed tm(ctx, "pack_c");
     HIP_TRY(ctx, launch_pack_c<T>(p->pack, C, Cp, p->maxblk, s));
+    if (bf16) HIP_TRY(ctx, launch_pack_cb(p->pack, C, Cb, p->maxblk * 4, s));
   }
   for (int t = 0; t < p->ntau; ++t) {
     {
       Timed tm(ctx, "pad_g");
-      HIP_TRY(ctx, launch_pad_g<T>(G_occ + t * gstride, G_un + t * gstride, p->nR, p->nb, p->nbp, Gp, s));
+      if (gexp) HIP_TRY(ctx, launch_gscale(G_occ + t * gstride, G_un + t * gstride, gstride, gpart, gexp, s));
+      HIP_TRY(ctx, launch_pad_g<T>(G_occ + t * gstride, G_un + t * gstride, p->nR, p->nb, p->nbp, gexp, Gp, s));
     }
     {
       Timed tm(ctx, "nstage");
@@ -194,9 +203,15 @@ static int build_impl(rpa_plan *p, const double *G_occ, const double *G_un, cons
     }
     {
       Timed tm(ctx, "fused");
-      for (const PlanGroup &g : p->groups)
-        HIP_TRY(ctx, launch_fused<T>(p->tb, p->group_items(g), g.mt, g.js, g.hc, Gp, Cp, Nb, negs, chi0_tau + t * chistride,
-                                     s));
+      for (const PlanGroup &g : p->groups) {
+        if (bf16)
+          HIP_TRY(ctx, launch_fused_bf16(p->tb, p->group_items(g), g.mt, fused_bf16_ks_class(g.js), g.hc,
+                                         (const float *)Gp, Cb, (const float *)Nb, negs, gexp,
+                                         chi0_tau + t * chistride, s));
+        else
+          HIP_TRY(ctx, launch_fused<T>(p->tb, p->group_items(g), g.mt, g.js, g.hc, Gp, Cp, Nb, negs, gexp,
+                                       chi0_tau + t * chistride, s));
+      }
     }
   }
   return RPA_OK;
@@ -246,7 +261,8 @@ int rpa_plan_create(rpa_ctx *ctx, const rpa_cell *cell, const rpa_lri_blocks *bl
   *out = nullptr;
   if (cell->natoms <= 0 || !cell->nao || !cell->naux) return fail(ctx, RPA_ERR_ARG, "bad cell");
   if (ntau <= 0) return fail(ctx, RPA_ERR_ARG, "ntau must be positive");
-  if (precision != RPA_FP64 && precision != RPA_FP32) return fail(ctx, RPA_ERR_ARG, "unknown precision");
+  if (precision != RPA_FP64 && precision != RPA_FP32 && precision != RPA_BF16X3)
+    return fail(ctx, RPA_ERR_ARG, "unknown precision");
   for (int d = 0; d < 3; ++d) {
     if (cell->mesh[d] <= 0) return fail(ctx, RPA_ERR_ARG, "mesh must be positive");
     if (cell->mesh[d] > 1023) return fail(ctx, RPA_ERR_UNSUPPORTED, "mesh dimensions must be below 1024");
@@ -298,6 +314,7 @@ int rpa_plan_create(rpa_ctx *ctx, const rpa_cell *cell, const rpa_lri_blocks *bl
   p->nblk = nblk;
   p->in_off.resize(nblk);
   p->out_off.resize(nblk);
+  p->cb_off.resize(nblk);
   p->blk_a.resize(nblk);
   p->blk_ni.resize(nblk);
   p->blk_nk.resize(nblk);
@@ -325,6 +342,9 @@ int rpa_plan_create(rpa_ctx *ctx, const rpa_cell *cell, const rpa_lri_blocks *bl
     const long long sz = (long long)p->cp_stride[I] * p->nao[K];   // packed: [k][(i, mu)], padded rows
     p->maxblk = std::max(p->maxblk, sz);
     acc += sz;
+    // split-BF16: [k][mu][hi, lo] rows of 2 x 16 hc slots
+    p->cb_off[b] = p->cb_elems;
+    p->cb_elems += (long long)p->nao[K] * p->naux[I] * 2 * 16 * (p->nao[I] > 16 ? 2 : 1);
   }
   p->cp_elems = acc;
   p->nbr_start.assign(na + 1, 0);
@@ -335,11 +355,13 @@ int rpa_plan_create(rpa_ctx *ctx, const rpa_cell *cell, const rpa_lri_blocks *bl
   p->nbr_K.resize(nblk);
   p->nbr_R1.resize(nblk);
   p->nbr_cp.resize(nblk);
+  p->nbr_cb.resize(nblk);
   for (int e = 0; e < nblk; ++e) {
     const int b = order[e];
     p->nbr_K[e] = blocks->K[b];
     p->nbr_R1[e] = fR[b];
     p->nbr_cp[e] = p->out_off[b];
+    p->nbr_cb[e] = p->cb_off[b];
   }
   p->nslices.assign(na, 0);
   for (int a = 0; a < na; ++a)
@@ -456,7 +478,8 @@ int rpa_plan_create(rpa_ctx *ctx, const rpa_cell *cell, const rpa_lri_blocks *bl
                s_pin = add(p->in_off.data(), nblk * 8), s_pout = add(p->out_off.data(), nblk * 8),
                s_pa = add(p->blk_a.data(), nblk * 4), s_pni = add(p->blk_ni.data(), nblk * 4),
                s_pnk = add(p->blk_nk.data(), nblk * 4), s_pst = add(p->blk_stride.data(), nblk * 4),
-               s_cst = add(p->cp_stride.data(), na * 4), s_nsl = add(p->nslices.data(), na * 4);
+               s_cst = add(p->cp_stride.data(), na * 4), s_nsl = add(p->nslices.data(), na * 4),
+               s_ncb = add(p->nbr_cb.data(), nblk * 8), s_pcb = add(p->cb_off.data(), nblk * 8);
   hipError_t he = hipSetDevice(ctx->device);
   if (he == hipSuccess) he = hipMalloc(&p->dtab, tot);
   if (he != hipSuccess) {
@@ -490,6 +513,7 @@ int rpa_plan_create(rpa_ctx *ctx, const rpa_cell *cell, const rpa_lri_blocks *bl
   tb.noff = I64(s_noff);
   tb.cp_stride = I32(s_cst);
   tb.nslices = I32(s_nsl);
+  tb.nbr_cb = I64(s_ncb);
   tb.natoms = na;
   tb.nb = p->nb;
   tb.nbp = p->nbp;
@@ -498,15 +522,18 @@ int rpa_plan_create(rpa_ctx *ctx, const rpa_cell *cell, const rpa_lri_blocks *bl
   tb.bvk = p->bvk;
   p->tiles = NTiles{I32(s_tV), I32(s_tM), I32(s_tN), (int)p->tileV.size()};
   p->items = PairItems{I32(s_iU), I32(s_iV), I32(s_iR), (int)p->itemU.size()};
-  p->pack = PackTables{I64(s_pin), I64(s_pout), I32(s_pa), I32(s_pni), I32(s_pnk), I32(s_pst), nblk};
+  p->pack = PackTables{I64(s_pin), I64(s_pout), I64(s_pcb), I32(s_pa), I32(s_pni), I32(s_pnk), I32(s_pst), nblk};
 
-  // workspace: packed C, padded G of one tau, N buffer for one tau
+  // workspace: packed C (N stage), split-BF16 C (BF16X3 fused kernel), padded G of one tau,
+  // N buffer for one tau, G scale (partial maxima and the two exponents)
   const size_t es = precision == RPA_FP64 ? 8 : 4;
   p->ws_cp = 0;
-  p->ws_g = align_up(p->cp_elems * es);
+  p->ws_cb = align_up(p->cp_elems * es);
+  p->ws_g = align_up(p->ws_cb + (precision == RPA_BF16X3 ? (size_t)p->cb_elems * 2 : 0));
   const size_t gbytes = 2 * (size_t)nR * p->nbp * p->nbp * es;
   p->ws_n = align_up(p->ws_g + gbytes);
-  p->ws_total = align_up(p->ws_n + (size_t)p->n_elems * es);
+  p->ws_sc = align_up(p->ws_n + (size_t)p->n_elems * es);
+  p->ws_total = align_up(p->ws_sc + 2 * kGscaleBlocks * sizeof(double) + 2 * sizeof(int));
   *workspace_bytes = p->ws_total;
   *out = p;
   return RPA_OK;
@@ -566,8 +593,8 @@ int build_chi0_tau(rpa_plan *p, double spin_factor, const double *G_occ, const d
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   char *ws = (char *)workspace;
   const double negs = -spin_factor;
-  if (p->prec == RPA_FP64) return build_impl<double>(p, G_occ, G_un, C, ws, negs, chi0_tau);
-  return build_impl<float>(p, G_occ, G_un, C, ws, negs, chi0_tau);
+  if (p->prec == RPA_FP64) return build_impl<double>(p, G_occ, G_un, C, ws, negs, chi0_tau, false);
+  return build_impl<float>(p, G_occ, G_un, C, ws, negs, chi0_tau, p->prec == RPA_BF16X3);
 }
 
 int chi0_tau_to_omega(rpa_ctx *ctx, int ntau, int nomega, size_t n, const double *gamma_cos,

@@ -1,0 +1,369 @@
+// Split-BF16 (3-term) variant of the fused chi kernel for gfx950.
+//
+// Same restructured Algorithm 1 as the FP32 fused kernel (one workgroup per (U <= V, R); Z terms
+// from two N blocks; K(R1) loop of O = [G^un | G^occ](R) [N^occ ; N^un] feeding chi += C O), with
+// both contractions of the loop on the bf16 MFMAs: every operand x is carried as hi + lo,
+// hi = bf16(x), lo = bf16(x - hi), and a product a b as a_hi b_hi + a_hi b_lo + a_lo b_hi
+// (the dropped a_lo b_lo is below 2^-16 relative), accumulated in FP32 and folded into FP64
+// after every neighbour block.  G is rescaled per tau by a power of two (pad_g), so the
+// split never meets the FP32 subnormal range; the epilogue removes the scale in FP64.
+// The N intermediate stays FP32 (written by the FP32 N stage) and is split in registers.
+#include "chi0_kernels.h"
+
+namespace {
+
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
+typedef short s4 __attribute__((ext_vector_type(4)));
+typedef unsigned u4 __attribute__((ext_vector_type(4)));
+
+// bf16 MFMAs with KW contraction values per lane: KW = 8 -> 16x16x32, KW = 4 -> 16x16x16.
+// Operand layout (measured on gfx950 with exact small integers): A lane l holds
+// A[l % 16][KW (l / 16) + e], B lane l holds B[KW (l / 16) + e][l % 16]; the FP32 result is
+// laid out as for the f32 16x16x4 MFMA (row 4 (l / 16) + r, column l % 16).
+template <int KW> struct BfMfma;
+template <> struct BfMfma<8> {
+  typedef bf8 vec;
+  static __device__ __forceinline__ f4 fma(vec a, vec b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct BfMfma<4> {
+  typedef bf4 vec;
+  static __device__ __forceinline__ f4 fma(vec a, vec b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(s4, a), __builtin_bit_cast(s4, b), c, 0, 0,
+                                                      0);
+  }
+};
+
+static __device__ __forceinline__ void split_bf16(float x, __bf16 &hi, __bf16 &lo) {
+  hi = (__bf16)x;                       // round to nearest even
+  lo = (__bf16)(x - (float)hi);         // x - hi is exact in FP32
+}
+
+// Contraction slot of NAO index i of U in the chi GEMM.  With HC i-tiles of 16, lane group g
+// holds as its KW = 4 HC values the O accumulator registers r of tiles h, i = 16 h + 4 g + r,
+// in the order 4 h + r, so O feeds the next MFMA without moving between lanes.
+static __device__ __forceinline__ int nao_of_slot(int slot, int hc) {
+  if (hc == 1) return slot;
+  const int g = slot / 8, h = (slot % 8) / 4, r = slot % 4;
+  return 16 * h + 4 * g + r;
+}
+
+// LRI blocks [mu][i][k] (FP64) -> per k, rows mu of 16 hc hi values then 16 hc lo values in
+// slot order (zero for slots past n_I), hc = 1 for n_I <= 16 else 2.
+__global__ __launch_bounds__(256) void pack_cb_kernel(PackTables pt, const double *__restrict__ C,
+                                                      __bf16 *__restrict__ Cb) {
+  const int b = blockIdx.x;
+  const int a = pt.a[b], ni = pt.ni[b], nk = pt.nk[b];
+  const int hc = ni > 16 ? 2 : 1, S = 16 * hc;
+  const long long total = (long long)nk * a * S;
+  const double *src = C + pt.in_off[b];
+  __bf16 *dst = Cb + pt.cb_off[b];
+  for (long long e = (long long)blockIdx.y * blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.y * blockDim.x) {
+    const int slot = (int)(e % S);
+    const long long t = e / S;
+    const int mu = (int)(t % a), k = (int)(t / a);
+    const int i = nao_of_slot(slot, hc);
+    const float x = i < ni ? (float)src[((long long)mu * ni + i) * nk + k] : 0.f;
+    __bf16 hi, lo;
+    split_bf16(x, hi, lo);
+    const long long row = ((long long)k * a + mu) * 2 * S;
+    dst[row + slot] = hi;
+    dst[row + S + slot] = lo;
+  }
+}
+
+constexpr int FB_THREADS = 512;
+
+// MT mu-tiles of U, KS O-GEMM steps of 32 over j' < 2 n_V, HC i-tiles of U (n_U <= 16 HC).
+template <int MT, int KS, int HC>
+__global__ __launch_bounds__(FB_THREADS) void fused_bf16_kernel(Chi0Tables tb, PairItems items,
+                                                                const float *__restrict__ Gp,
+                                                                const __bf16 *__restrict__ Cb,
+                                                                const float *__restrict__ Nbuf, double negs,
+                                                                const int *__restrict__ gexp,
+                                                                double *__restrict__ chi) {
+  constexpr int KW = 4 * HC;             // contraction values per lane in the chi GEMM
+  constexpr int S = 16 * HC;             // slots per C row and part (hi, lo)
+  constexpr int RS = 16 * HC + 4;        // LDS row stride in dwords: hi, lo, 4 dwords of padding
+  constexpr int CH = 4 * HC;             // 16-byte chunks per C row
+  constexpr int CG = 4;                  // mu-tiles per group of C fragment reads
+  typedef typename BfMfma<KW>::vec CVec;
+  typedef typename BfMfma<8>::vec NVec;
+  __shared__ __align__(16) unsigned Cs[2][kMaxNaux * RS];
+  __shared__ long long nbr_c[kMaxNbr], nbr_n[kMaxNbr];
+  __shared__ int nbr_k[kMaxNbr];
+
+  const int item = blockIdx.x;
+  const int U = items.U[item], V = items.V[item], R = items.R[item];
+  const int nU = tb.nao[U], aU = tb.naux[U], nV = tb.nao[V], aV = tb.naux[V];
+  const int natoms = tb.natoms, nR = tb.nR, nbp = tb.nbp;
+  const size_t plane = (size_t)nbp * nbp;
+  const int tid = threadIdx.x, lane = tid & 63, w = uniform(tid >> 6);
+  const int col = lane & 15, grp = lane >> 4;
+  const int nu = w * 16 + col;
+  const bool wave_active = w * 16 < aV;
+  const bool nu_ok = nu < aV;
+  const int e0 = tb.nbr_start[U], e1 = tb.nbr_start[U + 1];
+  const int ne = e1 - e0;
+
+  for (int e = tid; e < ne; e += FB_THREADS) {
+    const int K = tb.nbr_K[e0 + e];
+    nbr_k[e] = tb.nao[K];
+    nbr_c[e] = tb.nbr_cb[e0 + e];
+    nbr_n[e] = tb.noff[((size_t)V * natoms + K) * nR + tb.bvk.sub(tb.nbr_R1[e0 + e], R)];
+  }
+
+  // A operand of the O GEMM, split: A[i][j'] = G^un_ij(R) for j' = j < n_V, G^occ_ij(R) for
+  // j' = n_V + j; lane (col, grp) holds i = 16 h + col, j' = 32 ks + 8 grp + e
+  NVec ah[HC][KS], al[HC][KS];
+#pragma unroll
+  for (int h = 0; h < HC; ++h)
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int i = 16 * h + col, jp = 32 * ks + 8 * grp + e;
+        float v = 0.f;
+        if (i < nU && jp < 2 * nV) {
+          const int s = jp >= nV;
+          const int j = jp - s * nV;
+          v = Gp[(size_t)(1 - s) * nR * plane + (size_t)R * plane + (size_t)(tb.ao_off[U] + i) * nbp + tb.ao_off[V] + j];
+        }
+        __bf16 hi, lo;
+        split_bf16(v, hi, lo);
+        ah[h][ks][e] = hi;
+        al[h][ks][e] = lo;
+      }
+
+  f4 acc[MT];
+  double acc64[MT][4];
+#pragma unroll
+  for (int m = 0; m < MT; ++m) {
+    acc[m] = Mfma<float>::zero();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc64[m][r] = 0.0;
+  }
+  auto flush = [&]() {
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc64[m][r] += (double)acc[m][r];
+      acc[m] = Mfma<float>::zero();
+    }
+  };
+
+  // ---- Z terms (FP32 MFMA on the FP32 N blocks), as in the FP32 kernel
+  const int negR = tb.bvk.neg(R);
+  {
+    const float *NA = Nbuf + tb.noff[((size_t)U * natoms + V) * nR + R];
+    const float *NB = Nbuf + tb.noff[((size_t)V * natoms + U) * nR + negR];
+    if (wave_active) {
+      const int F = 2 * nU * nV;
+      for (int f0 = 0; f0 < F; f0 += 4) {
+        const int f = f0 + grp;
+        const bool fv = f < F;
+        int s = 0, i = 0, j = 0;
+        if (fv) {
+          s = f / (nU * nV);
+          const int rem = f - s * nU * nV;
+          i = rem / nV;
+          j = rem - i * nV;
+        }
+        const float bz = (fv && nu_ok) ? NB[((size_t)(i * 2 + 1 - s) * nV + j) * aV + nu] : 0.f;
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+          const int mu = 16 * m + col;
+          const float az = (fv && mu < aU) ? NA[((size_t)(j * 2 + s) * nU + i) * aU + mu] : 0.f;
+          acc[m] = Mfma<float>::fma(az, bz, acc[m]);
+        }
+      }
+    }
+    flush();
+  }
+  __syncthreads();   // neighbour table visible
+
+  // C slices: aU rows of CH 16-byte chunks, copied chunk for chunk into LDS rows of RS dwords.
+  // HC * 512 chunks cover all kMaxNaux rows; rows past aU read zero.
+  const unsigned sliceBytes = (unsigned)(aU * CH * 16);
+  const size_t sliceElems = (size_t)aU * 2 * S;
+  u4 rc[HC];
+  auto load_slice = [&](const __bf16 *src) {
+    const __amdgpu_buffer_rsrc_t r = buffer_view(src, sliceBytes);
+#pragma unroll
+    for (int q = 0; q < HC; ++q)
+      rc[q] = __builtin_bit_cast(u4, __builtin_amdgcn_raw_buffer_load_b128(r, (unsigned)((tid + q * FB_THREADS) * 16), 0, 0));
+  };
+  auto store_slice = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < HC; ++q) {
+      const int c = tid + q * FB_THREADS;
+      *reinterpret_cast<u4 *>(&Cs[buf][(c / CH) * RS + 4 * (c % CH)]) = rc[q];
+    }
+  };
+  // N rows (FP32): lane (nu, grp) holds j' = 32 ks + 8 grp + e; rows j' >= 2 n_V read zero
+  const size_t nstride = (size_t)2 * nV * aV;
+  const unsigned nview = wave_active ? (unsigned)(nstride * sizeof(float)) : 0u;
+  float nbA[KS * 8], nbB[KS * 8];
+  auto load_n = [&](const float *nrow, float *dst) {
+    const __amdgpu_buffer_rsrc_t r = buffer_view(nrow, nview);
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+        dst[ks * 8 + e] = buffer_load<float>(r, (unsigned)(((32 * ks + 8 * grp + e) * aV + nu) * sizeof(float)));
+  };
+  int e = 0, k = 0, cur = 0;
+  // one slice, as in the FP32 kernel: prefetch, O GEMM, chi += C O, stage the next C slice
+  auto slice = [&](const float *nbcur, float *nbnext, bool live) __attribute__((always_inline)) {
+    int e2 = e, k2 = k;
+    if (live) {
+      k2 = k + 1;
+      if (k2 == uniform(nbr_k[e])) {
+        e2 = e + 1;
+        k2 = 0;
+      }
+    }
+    const bool more = e2 < ne;
+    const int ea = more ? e2 : 0, ka = more ? k2 : 0;
+    load_slice(Cb + uniform(nbr_c[ea]) + (size_t)ka * sliceElems);
+    load_n(Nbuf + uniform(nbr_n[ea]) + (size_t)ka * nstride, nbnext);
+    __builtin_amdgcn_sched_barrier(0);
+    if (live && wave_active) {
+      NVec nh[KS], nl[KS];
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          __bf16 hi, lo;
+          split_bf16(nbcur[ks * 8 + q], hi, lo);
+          nh[ks][q] = hi;
+          nl[ks][q] = lo;
+        }
+      f4 o[HC];
+#pragma unroll
+      for (int h = 0; h < HC; ++h) o[h] = Mfma<float>::zero();
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+        for (int h = 0; h < HC; ++h) {
+          o[h] = BfMfma<8>::fma(ah[h][ks], nh[ks], o[h]);
+          o[h] = BfMfma<8>::fma(ah[h][ks], nl[ks], o[h]);
+          o[h] = BfMfma<8>::fma(al[h][ks], nh[ks], o[h]);
+        }
+      CVec bh, bl;
+#pragma unroll
+      for (int h = 0; h < HC; ++h)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          __bf16 hi, lo;
+          split_bf16(o[h][r], hi, lo);
+          bh[4 * h + r] = hi;
+          bl[4 * h + r] = lo;
+        }
+      const unsigned *cs = &Cs[cur][col * RS + grp * (KW / 2)];
+#pragma unroll
+      for (int m0 = 0; m0 < MT; m0 += CG) {
+        CVec chi_h[CG], chi_l[CG];
+#pragma unroll
+        for (int m = m0; m < m0 + CG && m < MT; ++m) {
+          chi_h[m - m0] = *reinterpret_cast<const CVec *>(cs + 16 * m * RS);
+          chi_l[m - m0] = *reinterpret_cast<const CVec *>(cs + 16 * m * RS + 8 * HC);
+        }
+#pragma unroll
+        for (int m = m0; m < m0 + CG && m < MT; ++m) acc[m] = BfMfma<KW>::fma(chi_h[m - m0], bh, acc[m]);
+#pragma unroll
+        for (int m = m0; m < m0 + CG && m < MT; ++m) acc[m] = BfMfma<KW>::fma(chi_h[m - m0], bl, acc[m]);
+#pragma unroll
+        for (int m = m0; m < m0 + CG && m < MT; ++m) acc[m] = BfMfma<KW>::fma(chi_l[m - m0], bh, acc[m]);
+      }
+    }
+    if (e2 != e) flush();
+    store_slice(cur ^ 1);
+    __syncthreads();
+    e = e2;
+    k = k2;
+    cur ^= 1;
+  };
+
+  const int nsl = tb.nslices[U];
+  if (ne > 0) {
+    load_slice(Cb + uniform(nbr_c[0]));
+    store_slice(0);
+    load_n(Nbuf + uniform(nbr_n[0]), nbA);
+    __syncthreads();
+    for (int t = 0; t < nsl; t += 2) {
+      slice(nbA, nbB, true);
+      slice(nbB, nbA, t + 1 < nsl);
+    }
+  }
+
+  // ---- epilogue: chi_UV(R) and chi_VU(-R) = chi_UV(R)^T, G scale removed
+  if (!wave_active || !nu_ok) return;
+  const double sc = ldexp(negs, -(gexp[0] + gexp[1]));
+  const size_t N = tb.nauxtot;
+  const int au0 = tb.aux_off[U], av0 = tb.aux_off[V];
+#pragma unroll
+  for (int m = 0; m < MT; ++m) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int mu = 16 * m + Mfma<float>::row(grp, r);
+      if (mu < aU) {
+        const double v = sc * acc64[m][r];
+        chi[((size_t)R * N + au0 + mu) * N + av0 + nu] = v;
+        if (U != V) chi[((size_t)negR * N + av0 + nu) * N + au0 + mu] = v;
+      }
+    }
+  }
+}
+
+template <int MT, int KS, int HC>
+void launch_one_bf16(const Chi0Tables &tb, const PairItems &items, const float *Gp, const __bf16 *Cb,
+                     const float *Nbuf, double negs, const int *gexp, double *chi, hipStream_t s) {
+  hipLaunchKernelGGL((fused_bf16_kernel<MT, KS, HC>), dim3(items.count), dim3(FB_THREADS), 0, s, tb, items, Gp, Cb,
+                     Nbuf, negs, gexp, chi);
+}
+
+template <int MT>
+hipError_t launch_ks_hc(int ks, int hc, const Chi0Tables &tb, const PairItems &items, const float *Gp,
+                        const __bf16 *Cb, const float *Nbuf, double negs, const int *gexp, double *chi,
+                        hipStream_t s) {
+  if (ks == 1 && hc == 1) launch_one_bf16<MT, 1, 1>(tb, items, Gp, Cb, Nbuf, negs, gexp, chi, s);
+  else if (ks == 1 && hc == 2) launch_one_bf16<MT, 1, 2>(tb, items, Gp, Cb, Nbuf, negs, gexp, chi, s);
+  else if (ks == 2 && hc == 1) launch_one_bf16<MT, 2, 1>(tb, items, Gp, Cb, Nbuf, negs, gexp, chi, s);
+  else if (ks == 2 && hc == 2) launch_one_bf16<MT, 2, 2>(tb, items, Gp, Cb, Nbuf, negs, gexp, chi, s);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+}  // namespace
+
+int fused_bf16_ks_class(int js_class) { return 4 * js_class <= 32 ? 1 : 2; }
+
+hipError_t launch_pack_cb(const PackTables &pt, const double *C, uint16_t *Cb, long long maxblk, hipStream_t s) {
+  if (pt.nblk == 0) return hipSuccess;
+  const int ychunks = (int)((maxblk + 256 * 16 - 1) / (256 * 16));
+  dim3 grid(pt.nblk, ychunks > 0 ? ychunks : 1);
+  hipLaunchKernelGGL(pack_cb_kernel, grid, dim3(256), 0, s, pt, C, reinterpret_cast<__bf16 *>(Cb));
+  return hipGetLastError();
+}
+
+hipError_t launch_fused_bf16(const Chi0Tables &tb, const PairItems &items, int mt, int ks, int hc, const float *Gp,
+                             const uint16_t *Cb, const float *Nbuf, double negs, const int *gexp, double *chi,
+                             hipStream_t s) {
+  if (items.count == 0) return hipSuccess;
+  const __bf16 *cb = reinterpret_cast<const __bf16 *>(Cb);
+  switch (mt) {
+    case 1: return launch_ks_hc<1>(ks, hc, tb, items, Gp, cb, Nbuf, negs, gexp, chi, s);
+    case 2: return launch_ks_hc<2>(ks, hc, tb, items, Gp, cb, Nbuf, negs, gexp, chi, s);
+    case 3: return launch_ks_hc<3>(ks, hc, tb, items, Gp, cb, Nbuf, negs, gexp, chi, s);
+    case 4: return launch_ks_hc<4>(ks, hc, tb, items, Gp, cb, Nbuf, negs, gexp, chi, s);
+    case 5: return launch_ks_hc<5>(ks, hc, tb, items, Gp, cb, Nbuf, negs, gexp, chi, s);
+    case 6: return launch_ks_hc<6>(ks, hc, tb, items, Gp, cb, Nbuf, negs, gexp, chi, s);
+    case 7: return launch_ks_hc<7>(ks, hc, tb, items, Gp, cb, Nbuf, negs, gexp, chi, s);
+    case 8: return launch_ks_hc<8>(ks, hc, tb, items, Gp, cb, Nbuf, negs, gexp, chi, s);
+    default: return hipErrorInvalidValue;
+  }
+}

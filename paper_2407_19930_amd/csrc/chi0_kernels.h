@@ -12,6 +12,7 @@ struct Chi0Tables {
   const int *nbr_start;                       // [natoms + 1]
   const int *nbr_K, *nbr_R1;                  // [nblk] second atom, folded lattice vector
   const long long *nbr_cp;                    // [nblk] offset of the packed block [k][i][mu]
+  const long long *nbr_cb;                    // [nblk] offset of the split-BF16 block (BF16X3 plans)
   const int *nslices;                         // [natoms] sum of nao[K] over the neighbours of U
   // contraction rows of the N-stage for atom V: r in [rows_start[V], rows_start[V+1])
   //   row r <-> (neighbour L(dL) of V, NAO l of L); row_info[r] = {G row ao_off[L] + l,
@@ -38,6 +39,7 @@ struct PairItems {   // fused-kernel items: atom pair U <= V and lattice vector 
 
 struct PackTables {  // repack of the caller's LRI blocks
   const long long *in_off, *out_off;
+  const long long *cb_off;                    // split-BF16 layout (BF16X3 plans)
   const int *a, *ni, *nk, *stride;
   int nblk;
 };
@@ -45,8 +47,14 @@ struct PackTables {  // repack of the caller's LRI blocks
 // launchers (return hipError_t of the launch)
 template <typename T>
 hipError_t launch_pack_c(const PackTables &pt, const double *C, T *Cp, long long maxblk, hipStream_t s);
+// Per-tau power-of-two scale of G: gexp[s] = e with max |G^s| 2^e in [1, 2) (0 for an all-zero
+// G); part holds 2 * kGscaleBlocks doubles of partial maxima.
+constexpr int kGscaleBlocks = 256;
+hipError_t launch_gscale(const double *Gocc, const double *Gun, size_t n, double *part, int *gexp, hipStream_t s);
+// Gp[s][R][nbp][nbp] = G^s 2^gexp[s] in the compute precision (gexp may be null: no scale).
 template <typename T>
-hipError_t launch_pad_g(const double *Gocc, const double *Gun, int nR, int nb, int nbp, T *Gp, hipStream_t s);
+hipError_t launch_pad_g(const double *Gocc, const double *Gun, int nR, int nb, int nbp, const int *gexp, T *Gp,
+                        hipStream_t s);
 template <typename T>
 hipError_t launch_nstage(const Chi0Tables &tb, const NTiles &tiles, const T *Gp, const T *Cp, T *Nbuf,
                          hipStream_t s);
@@ -54,9 +62,18 @@ hipError_t launch_nstage(const Chi0Tables &tb, const NTiles &tiles, const T *Gp,
 // mt = fused_mt_class(naux_U), js = fused_js_class(nao_V) and hc = i-tiles of U (1 or 2).
 int fused_mt_class(int naux);
 int fused_js_class(int nao);
+// chi is written as negs 2^-(gexp[0] + gexp[1]) times the contraction (gexp may be null).
 template <typename T>
 hipError_t launch_fused(const Chi0Tables &tb, const PairItems &items, int mt, int js, int hc, const T *Gp,
-                        const T *Cp, const T *Nbuf, double negs, double *chi, hipStream_t s);
+                        const T *Cp, const T *Nbuf, double negs, const int *gexp, double *chi, hipStream_t s);
+
+// Split-BF16 (3-term) fused kernel on FP32 G and N, with C packed by launch_pack_cb (bf16 bits
+// as uint16_t); ks = O-GEMM steps of 32 for the group's js class.
+int fused_bf16_ks_class(int js_class);
+hipError_t launch_pack_cb(const PackTables &pt, const double *C, uint16_t *Cb, long long maxblk, hipStream_t s);
+hipError_t launch_fused_bf16(const Chi0Tables &tb, const PairItems &items, int mt, int ks, int hc, const float *Gp,
+                             const uint16_t *Cb, const float *Nbuf, double negs, const int *gexp, double *chi,
+                             hipStream_t s);
 
 // compile-time limits of the kernels
 constexpr int kMaxNao = 32;     // NAOs per atom

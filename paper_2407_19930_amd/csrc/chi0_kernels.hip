@@ -44,11 +44,59 @@ __global__ __launch_bounds__(256) void pack_c_kernel(PackTables pt, const double
   }
 }
 
-// G^occ, G^un of one tau (FP64, [nR][nb][nb] each) -> Gp[s][R][nbp][nbp] in the compute
-// precision, s = 0 occ, 1 un, zero padding up to nbp (a multiple of 8).
+// Per-tau scale of G (north of the FP32 subnormal range for any tau): partial maxima of |G^s|,
+// then one block turns them into the exponents e_s with max |G^s| 2^e_s in [1, 2).
+constexpr int GS_THREADS = 256;
+__global__ __launch_bounds__(GS_THREADS) void gmax_kernel(const double *__restrict__ Gocc,
+                                                          const double *__restrict__ Gun, size_t n,
+                                                          double *__restrict__ part) {
+  __shared__ double red[2][GS_THREADS];
+  double m0 = 0.0, m1 = 0.0;
+  for (size_t e = (size_t)blockIdx.x * GS_THREADS + threadIdx.x; e < n; e += (size_t)gridDim.x * GS_THREADS) {
+    m0 = fmax(m0, fabs(Gocc[e]));
+    m1 = fmax(m1, fabs(Gun[e]));
+  }
+  red[0][threadIdx.x] = m0;
+  red[1][threadIdx.x] = m1;
+  __syncthreads();
+  for (int h = GS_THREADS / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      red[0][threadIdx.x] = fmax(red[0][threadIdx.x], red[0][threadIdx.x + h]);
+      red[1][threadIdx.x] = fmax(red[1][threadIdx.x], red[1][threadIdx.x + h]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 2) part[threadIdx.x * kGscaleBlocks + blockIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(kGscaleBlocks) void gexp_kernel(const double *__restrict__ part, int *__restrict__ gexp) {
+  __shared__ double red[2][kGscaleBlocks];
+  red[0][threadIdx.x] = part[threadIdx.x];
+  red[1][threadIdx.x] = part[kGscaleBlocks + threadIdx.x];
+  __syncthreads();
+  for (int h = kGscaleBlocks / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      red[0][threadIdx.x] = fmax(red[0][threadIdx.x], red[0][threadIdx.x + h]);
+      red[1][threadIdx.x] = fmax(red[1][threadIdx.x], red[1][threadIdx.x + h]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 2) {
+    const double m = red[threadIdx.x][0];
+    int x = 1;
+    if (m > 0.0 && isfinite(m)) frexp(m, &x);   // m = f 2^x, f in [0.5, 1)
+    gexp[threadIdx.x] = 1 - x;
+  }
+}
+
+// G^occ, G^un of one tau (FP64, [nR][nb][nb] each) -> Gp[s][R][nbp][nbp] = G^s 2^gexp[s] in the
+// compute precision (no scale for a null gexp), s = 0 occ, 1 un, zero padding up to nbp (a
+// multiple of 8).
 template <typename T>
 __global__ __launch_bounds__(256) void pad_g_kernel(const double *__restrict__ Gocc, const double *__restrict__ Gun,
-                                                    int nR, int nb, int nbp, T *__restrict__ Gp) {
+                                                    int nR, int nb, int nbp, const int *__restrict__ gexp,
+                                                    T *__restrict__ Gp) {
+  const double sc0 = gexp ? ldexp(1.0, gexp[0]) : 1.0, sc1 = gexp ? ldexp(1.0, gexp[1]) : 1.0;
   const size_t total = (size_t)2 * nR * nbp * nbp;
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
     const int c = (int)(e % nbp);
@@ -57,7 +105,7 @@ __global__ __launch_bounds__(256) void pad_g_kernel(const double *__restrict__ G
     const size_t sR = t / nbp;
     const int R = (int)(sR % nR), s = (int)(sR / nR);
     T v = T(0);
-    if (r < nb && c < nb) v = (T)(s ? Gun : Gocc)[((size_t)R * nb + r) * nb + c];
+    if (r < nb && c < nb) v = (T)((s ? Gun : Gocc)[((size_t)R * nb + r) * nb + c] * (s ? sc1 : sc0));
     Gp[e] = v;
   }
 }
@@ -268,31 +316,12 @@ template <> struct Lds<double> {
   }
 };
 
-// wave-uniform copies of values every lane holds alike (loop state from LDS tables)
-__device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
-__device__ __forceinline__ long long uniform(long long x) {
-  const unsigned lo = __builtin_amdgcn_readfirstlane((int)(x & 0xffffffffll));
-  const unsigned hi = __builtin_amdgcn_readfirstlane((int)(x >> 32));
-  return (long long)(((unsigned long long)hi << 32) | lo);
-}
-// raw buffer view of [p, p + nbytes): loads at byte offsets >= nbytes return zero without a
-// memory access, so the masked loads of the slice loop need no branches
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_view(const void *p, unsigned nbytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)nbytes, 0x00020000);
-}
-template <typename T> __device__ __forceinline__ T buffer_load(__amdgpu_buffer_rsrc_t r, unsigned off);
-template <> __device__ __forceinline__ float buffer_load<float>(__amdgpu_buffer_rsrc_t r, unsigned off) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
-}
-template <> __device__ __forceinline__ double buffer_load<double>(__amdgpu_buffer_rsrc_t r, unsigned off) {
-  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
-}
-
 template <typename T, bool kSplit, int MT, int JS, int HC>
 __global__ __launch_bounds__(FU_THREADS) void fused_kernel(Chi0Tables tb, PairItems items,
                                                            const T *__restrict__ Gp,
                                                            const T *__restrict__ Cp,
                                                            const T *__restrict__ Nbuf, double negs,
+                                                           const int *__restrict__ gexp,
                                                            double *__restrict__ chi) {
   typedef typename Mfma<T>::acc Acc;
   constexpr int IP = Lds<T>::IP;
@@ -499,8 +528,9 @@ __global__ __launch_bounds__(FU_THREADS) void fused_kernel(Chi0Tables tb, PairIt
     }
   }
 
-  // ---- epilogue: chi_UV(R) and chi_VU(-R) = chi_UV(R)^T
+  // ---- epilogue: chi_UV(R) and chi_VU(-R) = chi_UV(R)^T, G scale removed
   if (!wave_active || !nu_ok) return;
+  const double sc = gexp ? ldexp(negs, -(gexp[0] + gexp[1])) : negs;
   const size_t N = tb.nauxtot;
   const int au0 = tb.aux_off[U], av0 = tb.aux_off[V];
 #pragma unroll
@@ -509,7 +539,7 @@ __global__ __launch_bounds__(FU_THREADS) void fused_kernel(Chi0Tables tb, PairIt
     for (int r = 0; r < 4; ++r) {
       const int mu = 16 * m + Mfma<T>::row(grp, r);
       if (mu < aU) {
-        const double v = negs * (kSplit ? acc64[m][r] : (double)acc[m][r]);
+        const double v = sc * (kSplit ? acc64[m][r] : (double)acc[m][r]);
         chi[((size_t)R * N + au0 + mu) * N + av0 + nu] = v;
         if (U != V) chi[((size_t)negR * N + av0 + nu) * N + au0 + mu] = v;
       }
@@ -528,11 +558,18 @@ hipError_t launch_pack_c(const PackTables &pt, const double *C, T *Cp, long long
   return hipGetLastError();
 }
 
+hipError_t launch_gscale(const double *Gocc, const double *Gun, size_t n, double *part, int *gexp, hipStream_t s) {
+  hipLaunchKernelGGL(gmax_kernel, dim3(kGscaleBlocks), dim3(GS_THREADS), 0, s, Gocc, Gun, n, part);
+  hipLaunchKernelGGL(gexp_kernel, dim3(1), dim3(kGscaleBlocks), 0, s, part, gexp);
+  return hipGetLastError();
+}
+
 template <typename T>
-hipError_t launch_pad_g(const double *Gocc, const double *Gun, int nR, int nb, int nbp, T *Gp, hipStream_t s) {
+hipError_t launch_pad_g(const double *Gocc, const double *Gun, int nR, int nb, int nbp, const int *gexp, T *Gp,
+                        hipStream_t s) {
   const size_t n = (size_t)2 * nR * nbp * nbp;
   const int blocks = (int)std::min<size_t>((n + 255) / 256, 65536);
-  hipLaunchKernelGGL(pad_g_kernel<T>, dim3(blocks), dim3(256), 0, s, Gocc, Gun, nR, nb, nbp, Gp);
+  hipLaunchKernelGGL(pad_g_kernel<T>, dim3(blocks), dim3(256), 0, s, Gocc, Gun, nR, nb, nbp, gexp, Gp);
   return hipGetLastError();
 }
 
@@ -570,25 +607,25 @@ int fused_js_class(int nao) {
 
 template <typename T, int MT, int JS>
 static void launch_one(int hc, const Chi0Tables &tb, const PairItems &items, const T *Gp, const T *Cp,
-                       const T *Nbuf, double negs, double *chi, hipStream_t s) {
+                       const T *Nbuf, double negs, const int *gexp, double *chi, hipStream_t s) {
   if (hc == 1)
     hipLaunchKernelGGL((fused_kernel<T, sizeof(T) == 4, MT, JS, 1>), dim3(items.count), dim3(FU_THREADS), 0, s, tb,
-                       items, Gp, Cp, Nbuf, negs, chi);
+                       items, Gp, Cp, Nbuf, negs, gexp, chi);
   else
     hipLaunchKernelGGL((fused_kernel<T, sizeof(T) == 4, MT, JS, 2>), dim3(items.count), dim3(FU_THREADS), 0, s, tb,
-                       items, Gp, Cp, Nbuf, negs, chi);
+                       items, Gp, Cp, Nbuf, negs, gexp, chi);
 }
 
 template <typename T, int MT>
 static hipError_t launch_js(int js, int hc, const Chi0Tables &tb, const PairItems &items, const T *Gp, const T *Cp,
-                            const T *Nbuf, double negs, double *chi, hipStream_t s) {
+                            const T *Nbuf, double negs, const int *gexp, double *chi, hipStream_t s) {
   switch (js) {
-    case 2: launch_one<T, MT, 2>(hc, tb, items, Gp, Cp, Nbuf, negs, chi, s); break;
-    case 4: launch_one<T, MT, 4>(hc, tb, items, Gp, Cp, Nbuf, negs, chi, s); break;
-    case 7: launch_one<T, MT, 7>(hc, tb, items, Gp, Cp, Nbuf, negs, chi, s); break;
-    case 10: launch_one<T, MT, 10>(hc, tb, items, Gp, Cp, Nbuf, negs, chi, s); break;
-    case 13: launch_one<T, MT, 13>(hc, tb, items, Gp, Cp, Nbuf, negs, chi, s); break;
-    case 16: launch_one<T, MT, 16>(hc, tb, items, Gp, Cp, Nbuf, negs, chi, s); break;
+    case 2: launch_one<T, MT, 2>(hc, tb, items, Gp, Cp, Nbuf, negs, gexp, chi, s); break;
+    case 4: launch_one<T, MT, 4>(hc, tb, items, Gp, Cp, Nbuf, negs, gexp, chi, s); break;
+    case 7: launch_one<T, MT, 7>(hc, tb, items, Gp, Cp, Nbuf, negs, gexp, chi, s); break;
+    case 10: launch_one<T, MT, 10>(hc, tb, items, Gp, Cp, Nbuf, negs, gexp, chi, s); break;
+    case 13: launch_one<T, MT, 13>(hc, tb, items, Gp, Cp, Nbuf, negs, gexp, chi, s); break;
+    case 16: launch_one<T, MT, 16>(hc, tb, items, Gp, Cp, Nbuf, negs, gexp, chi, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -596,30 +633,32 @@ static hipError_t launch_js(int js, int hc, const Chi0Tables &tb, const PairItem
 
 template <typename T>
 hipError_t launch_fused(const Chi0Tables &tb, const PairItems &items, int mt, int js, int hc, const T *Gp,
-                        const T *Cp, const T *Nbuf, double negs, double *chi, hipStream_t s) {
+                        const T *Cp, const T *Nbuf, double negs, const int *gexp, double *chi, hipStream_t s) {
   if (items.count == 0) return hipSuccess;
   switch (mt) {
-    case 1: return launch_js<T, 1>(js, hc, tb, items, Gp, Cp, Nbuf, negs, chi, s);
-    case 2: return launch_js<T, 2>(js, hc, tb, items, Gp, Cp, Nbuf, negs, chi, s);
-    case 3: return launch_js<T, 3>(js, hc, tb, items, Gp, Cp, Nbuf, negs, chi, s);
-    case 4: return launch_js<T, 4>(js, hc, tb, items, Gp, Cp, Nbuf, negs, chi, s);
-    case 5: return launch_js<T, 5>(js, hc, tb, items, Gp, Cp, Nbuf, negs, chi, s);
-    case 6: return launch_js<T, 6>(js, hc, tb, items, Gp, Cp, Nbuf, negs, chi, s);
-    case 7: return launch_js<T, 7>(js, hc, tb, items, Gp, Cp, Nbuf, negs, chi, s);
-    case 8: return launch_js<T, 8>(js, hc, tb, items, Gp, Cp, Nbuf, negs, chi, s);
+    case 1: return launch_js<T, 1>(js, hc, tb, items, Gp, Cp, Nbuf, negs, gexp, chi, s);
+    case 2: return launch_js<T, 2>(js, hc, tb, items, Gp, Cp, Nbuf, negs, gexp, chi, s);
+    case 3: return launch_js<T, 3>(js, hc, tb, items, Gp, Cp, Nbuf, negs, gexp, chi, s);
+    case 4: return launch_js<T, 4>(js, hc, tb, items, Gp, Cp, Nbuf, negs, gexp, chi, s);
+    case 5: return launch_js<T, 5>(js, hc, tb, items, Gp, Cp, Nbuf, negs, gexp, chi, s);
+    case 6: return launch_js<T, 6>(js, hc, tb, items, Gp, Cp, Nbuf, negs, gexp, chi, s);
+    case 7: return launch_js<T, 7>(js, hc, tb, items, Gp, Cp, Nbuf, negs, gexp, chi, s);
+    case 8: return launch_js<T, 8>(js, hc, tb, items, Gp, Cp, Nbuf, negs, gexp, chi, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 template hipError_t launch_pack_c<double>(const PackTables &, const double *, double *, long long, hipStream_t);
 template hipError_t launch_pack_c<float>(const PackTables &, const double *, float *, long long, hipStream_t);
-template hipError_t launch_pad_g<double>(const double *, const double *, int, int, int, double *, hipStream_t);
-template hipError_t launch_pad_g<float>(const double *, const double *, int, int, int, float *, hipStream_t);
+template hipError_t launch_pad_g<double>(const double *, const double *, int, int, int, const int *, double *,
+                                         hipStream_t);
+template hipError_t launch_pad_g<float>(const double *, const double *, int, int, int, const int *, float *,
+                                        hipStream_t);
 template hipError_t launch_nstage<double>(const Chi0Tables &, const NTiles &, const double *, const double *,
                                           double *, hipStream_t);
 template hipError_t launch_nstage<float>(const Chi0Tables &, const NTiles &, const float *, const float *, float *,
                                          hipStream_t);
 template hipError_t launch_fused<double>(const Chi0Tables &, const PairItems &, int, int, int, const double *,
-                                         const double *, const double *, double, double *, hipStream_t);
+                                         const double *, const double *, double, const int *, double *, hipStream_t);
 template hipError_t launch_fused<float>(const Chi0Tables &, const PairItems &, int, int, int, const float *,
-                                        const float *, const float *, double, double *, hipStream_t);
+                                        const float *, const float *, double, const int *, double *, hipStream_t);

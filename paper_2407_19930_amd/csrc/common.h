@@ -55,3 +55,23 @@ struct Bvk {
   }
   __host__ __device__ __forceinline__ int neg(int r) const { return sub(0, r); }
 };
+
+// wave-uniform copies of values every lane holds alike (loop state from LDS tables)
+static __device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
+static __device__ __forceinline__ long long uniform(long long x) {
+  const unsigned lo = __builtin_amdgcn_readfirstlane((int)(x & 0xffffffffll));
+  const unsigned hi = __builtin_amdgcn_readfirstlane((int)(x >> 32));
+  return (long long)(((unsigned long long)hi << 32) | lo);
+}
+// raw buffer view of [p, p + nbytes): loads at byte offsets >= nbytes return zero without a
+// memory access, so the masked loads of the slice loop need no branches
+static __device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_view(const void *p, unsigned nbytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)nbytes, 0x00020000);
+}
+template <typename T> __device__ __forceinline__ T buffer_load(__amdgpu_buffer_rsrc_t r, unsigned off);
+template <> __device__ __forceinline__ float buffer_load<float>(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+template <> __device__ __forceinline__ double buffer_load<double>(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}

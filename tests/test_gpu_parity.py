@@ -1,7 +1,7 @@
 """GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the same seeded inputs.
 
 Tolerances (stated by the target of the path): FP64 path relative Frobenius error of chi <= 1e-11;
-FP32 path <= 1e-5 and |dE_c| <= 1e-6 Ha/atom."""
+mixed paths (FP32, split-BF16 3-term) <= 1e-5 and |dE_c| <= 1e-6 Ha/atom."""
 import sys
 
 import numpy as np
@@ -12,12 +12,15 @@ from oracle.energy import correlation_energy, ec_terms_lu
 from oracle.pipeline import ec_from_chi_tau
 from oracle.transforms import cos_transform, fourier_R_to_q
 from tests._util import micro, cfg
-from tests._gpu import gpu_chi_tau, gpu_pipeline, rel
+from tests._gpu import device_inputs, gpu_chi_tau, gpu_pipeline, rel
 
 pytestmark = pytest.mark.gpu
 
 FP64_TOL = 1e-11
 FP32_TOL = 1e-5
+CHI_TOL = {"fp64": FP64_TOL, "fp32": FP32_TOL, "bf16x3": FP32_TOL}
+EC_TOL = {"fp64": 1e-10, "fp32": 1e-6, "bf16x3": 1e-6}      # Ha/atom
+PRECISIONS = ["fp64", "fp32", "bf16x3"]
 
 MICRO = [
     dict(),                                                                        # 2 atoms, mesh 3x2x1
@@ -45,7 +48,7 @@ def _oracle_chi(inp, key, cache):
 
 
 @pytest.mark.parametrize("idx", range(len(MICRO)))
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("precision", PRECISIONS)
 def test_chi_tau_micro(idx, precision, oracle_cache):
     spec = MICRO[idx]
     inp = micro(**spec)
@@ -56,10 +59,10 @@ def test_chi_tau_micro(idx, precision, oracle_cache):
     err = rel(got, ref)
     say("  rel err", err)
     assert np.all(np.isfinite(got))
-    assert err <= (FP64_TOL if precision == "fp64" else FP32_TOL)
+    assert err <= CHI_TOL[precision]
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("precision", PRECISIONS)
 def test_chi_tau_tiny_workload(precision, oracle_cache):
     inp = cfg(0)
     say("case chi_tau tiny workload", precision)
@@ -69,7 +72,24 @@ def test_chi_tau_tiny_workload(precision, oracle_cache):
     err = rel(got, ref)
     per_tau = max(rel(got[t], ref[t]) for t in range(inp.ntau))
     say("  rel err", err, "max per-tau", per_tau, "flops", plan.flops())
-    assert err <= (FP64_TOL if precision == "fp64" else FP32_TOL)
+    assert err <= CHI_TOL[precision]
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_tau_rescale_is_exact(precision):
+    """G scaled by 2^-80: without the per-tau power-of-two scale the FP32 products (~1e-54) would
+    underflow to zero; with it every device intermediate is unchanged, so chi must come out
+    scaled by exactly 2^-160 (bitwise equal after undoing it)."""
+    inp = micro(**MICRO[3])
+    say("case tau rescale", precision)
+    d = device_inputs(inp)
+    a, _, ctx = gpu_chi_tau(inp, precision, dev_in=d)
+    s = 2.0 ** -80
+    b, _, _ = gpu_chi_tau(inp, precision, ctx=ctx, dev_in=dict(Gocc=d["Gocc"] * s, Gun=d["Gun"] * s, C=d["C"]))
+    scaled = b * 2.0 ** 160
+    say("  max abs chi", float(a.abs().max()), "max abs difference", float((scaled - a).abs().max()))
+    assert float(a.abs().max()) > 0
+    assert bool((scaled == a).all())
 
 
 def test_transforms_match_oracle_on_same_input():
@@ -111,7 +131,7 @@ def test_correlation_energy_matches_lu_on_same_input():
     assert np.max(np.abs(perq - perq_ref)) <= 1e-11 * abs(ec_ref)
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("precision", PRECISIONS)
 def test_pipeline_tiny_workload(precision, oracle_cache):
     inp = cfg(0)
     say("case pipeline tiny", precision)
@@ -119,7 +139,7 @@ def test_pipeline_tiny_workload(precision, oracle_cache):
     out = gpu_pipeline(inp, precision)
     d = abs(out["ec"] - ec_ref) / inp.natoms
     say("  E_c/atom gpu", out["ec"] / inp.natoms, "oracle", ec_ref / inp.natoms, "dE/atom", d)
-    assert d <= (1e-10 if precision == "fp64" else 1e-6)
+    assert d <= EC_TOL[precision]
 
 
 def test_errors_are_reported():
@@ -151,9 +171,10 @@ def test_errors_are_reported():
     assert e.value.code == RPA_ERR_NOT_HPD
 
 
-def test_deterministic_bitwise():
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_deterministic_bitwise(precision):
     inp = micro(**MICRO[3])
-    say("case determinism")
-    a, _, ctx = gpu_chi_tau(inp, "fp32")
-    b, _, _ = gpu_chi_tau(inp, "fp32", ctx)
+    say("case determinism", precision)
+    a, _, ctx = gpu_chi_tau(inp, precision)
+    b, _, _ = gpu_chi_tau(inp, precision, ctx)
     assert bool((a == b).all())
