@@ -180,6 +180,55 @@ RPA_API int rpa_correlation_energy(rpa_ctx *ctx, int n, int nq, int nomega, cons
                            const double *chi0_q, const double *v_q, void *workspace,
                            size_t workspace_bytes, double *Ec, double *Ec_q);
 
+/* ---- Batches of independent cells -------------------------------------------
+ * The whole path (build_chi0_tau, chi0_tau_to_omega, chi0_R_to_q and the energy
+ * stage of rpa_correlation_energy) of many cells, captured once into one HIP graph
+ * and replayed with a single graph launch.  Cells are assigned to lanes: the cells
+ * of a lane run one after another in the order given, lanes run concurrently
+ * (one stream branch per lane inside the graph).  Cells of one lane may therefore
+ * share scratch buffers (chi arrays, workspaces); cells of different lanes must not.
+ * Small per-cell host arrays are copied at creation; device pointers are captured
+ * into the graph and must stay valid, with the same sizes, while the batch lives. */
+typedef struct rpa_batch rpa_batch;
+
+typedef struct {
+  rpa_plan *plan;           /* the cell's plan (cell shape, ntau, precision); same context */
+  int lane;                 /* 0 <= lane < nlanes */
+  int nomega, nq;
+  double spin_factor;
+  const double *gamma_cos;  /* host [nomega][ntau], as chi0_tau_to_omega */
+  const double *womega;     /* host [nomega] */
+  const double *q_frac;     /* host [3*nq] */
+  const double *G_occ, *G_un, *C;   /* device, as build_chi0_tau */
+  const double *v_q;        /* device complex128 [nq][n][n] (n = the cell's naux total) */
+  void *build_workspace;    /* device, >= the plan's workspace size */
+  size_t build_workspace_bytes;
+  double *chi0_tau;         /* device [ntau][nR][n][n] */
+  double *chi0_omega;       /* device [nomega][nR][n][n] */
+  double *chi0_q;           /* device complex128 [nomega][nq][n][n]; may alias chi0_tau when
+                               that buffer holds 2 nomega nR n^2 doubles (chi0_tau is dead
+                               once chi0_omega is built) */
+  void *ec_workspace;       /* device, >= rpa_ec_workspace_size(n, nq, nomega) with one
+                               frequency per batch (see rpa_correlation_energy) */
+  size_t ec_workspace_bytes;
+} rpa_batch_cell;
+
+/* Validate the cells, copy their host arrays to the device and capture the graph
+ * (nothing runs yet).  Errors: RPA_ERR_ARG, RPA_ERR_SHAPE, RPA_ERR_WORKSPACE,
+ * RPA_ERR_HIP. */
+RPA_API int rpa_batch_create(rpa_ctx *ctx, int ncells, int nlanes, const rpa_batch_cell *cells,
+                             rpa_batch **batch);
+/* Launch the graph on the context's stream (asynchronous). */
+RPA_API int rpa_batch_run(rpa_batch *batch);
+/* Wait for the stream, check every cell's status flags and copy E_c per cell
+ * (host [ncells]) and, if Ec_q is not NULL, the per-q terms of all cells
+ * concatenated in cell order (host [sum of nq]).  Errors: RPA_ERR_NOT_HPD,
+ * RPA_ERR_NONFINITE (the message names the cell), RPA_ERR_HIP. */
+RPA_API int rpa_batch_result(rpa_batch *batch, double *Ec, double *Ec_q);
+/* Waits for the device, then frees the graph, the lane streams and the batch's
+ * small device buffers.  The plans stay owned by the caller. */
+RPA_API int rpa_batch_destroy(rpa_batch *batch);
+
 #ifdef __cplusplus
 }
 #endif

@@ -23,7 +23,8 @@ PRECISIONS = {"fp64": RPA_FP64, "fp32": RPA_FP32, "bf16x3": RPA_BF16X3}
 EXPORTED = ["rpa_create", "rpa_set_stream", "rpa_destroy", "rpa_last_error", "rpa_plan_create",
             "rpa_plan_destroy", "rpa_plan_flops", "rpa_plan_stage_flops", "rpa_profile", "rpa_profile_read",
             "build_chi0_tau", "chi0_tau_to_omega", "chi0_R_to_q", "rpa_ec_workspace_size",
-            "rpa_correlation_energy"]
+            "rpa_correlation_energy", "rpa_batch_create", "rpa_batch_run", "rpa_batch_result",
+            "rpa_batch_destroy"]
 
 
 class RpaError(RuntimeError):
@@ -40,6 +41,16 @@ class _Cell(ctypes.Structure):
 class _Blocks(ctypes.Structure):
     _fields_ = [("nblk", ctypes.c_int), ("I", ctypes.POINTER(ctypes.c_int)), ("K", ctypes.POINTER(ctypes.c_int)),
                 ("R", ctypes.POINTER(ctypes.c_int)), ("off", ctypes.POINTER(ctypes.c_longlong))]
+
+
+class _BatchCell(ctypes.Structure):
+    _fields_ = [("plan", ctypes.c_void_p), ("lane", ctypes.c_int), ("nomega", ctypes.c_int), ("nq", ctypes.c_int),
+                ("spin_factor", ctypes.c_double), ("gamma_cos", ctypes.c_void_p), ("womega", ctypes.c_void_p),
+                ("q_frac", ctypes.c_void_p), ("G_occ", ctypes.c_void_p), ("G_un", ctypes.c_void_p),
+                ("C", ctypes.c_void_p), ("v_q", ctypes.c_void_p), ("build_workspace", ctypes.c_void_p),
+                ("build_workspace_bytes", ctypes.c_size_t), ("chi0_tau", ctypes.c_void_p),
+                ("chi0_omega", ctypes.c_void_p), ("chi0_q", ctypes.c_void_p), ("ec_workspace", ctypes.c_void_p),
+                ("ec_workspace_bytes", ctypes.c_size_t)]
 
 
 _lib = None
@@ -74,6 +85,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.rpa_ec_workspace_size.argtypes = [i, i, i]
     lib.rpa_ec_workspace_size.restype = sz
     lib.rpa_correlation_energy.argtypes = [vp, i, i, i, vp, vp, vp, vp, sz, ctypes.POINTER(dp), vp]
+    lib.rpa_batch_create.argtypes = [vp, i, i, ctypes.POINTER(_BatchCell), ctypes.POINTER(vp)]
+    lib.rpa_batch_run.argtypes = [vp]
+    lib.rpa_batch_result.argtypes = [vp, vp, vp]
+    lib.rpa_batch_destroy.argtypes = [vp]
     for name in EXPORTED:
         if name not in ("rpa_destroy", "rpa_last_error", "rpa_ec_workspace_size"):
             getattr(lib, name).restype = ctypes.c_int
@@ -114,6 +129,7 @@ class Context:
             raise RpaError(rc, "rpa_create failed")
         self.h = h
         self._plans = weakref.WeakSet()
+        self._batches = weakref.WeakSet()
 
     def check(self, rc):
         if rc != RPA_OK:
@@ -131,6 +147,8 @@ class Context:
 
     def close(self):
         if getattr(self, "h", None):
+            for b in list(getattr(self, "_batches", ())):
+                b.close()               # batches hold graphs that read the plans' tables
             for p in list(getattr(self, "_plans", ())):
                 p.close()               # plans hold a pointer to the context
             self.lib.rpa_destroy(self.h)
@@ -255,3 +273,62 @@ def rpa_correlation_energy(ctx: Context, womega, chi0_q, v_q, workspace):
                                              workspace.numel() * workspace.element_size(), ctypes.byref(ec),
                                              ecq.ctypes.data_as(ctypes.c_void_p)))
     return ec.value, ecq
+
+
+class Batch:
+    """rpa_batch_create / run / result / destroy: many cells in one captured HIP graph.
+
+    `cells` is a list of dicts with the fields of rpa_batch_cell: plan, lane, spin_factor,
+    gamma_cos [nomega, ntau], womega [nomega], q_frac [nq, 3] (host arrays); G_occ, G_un, C,
+    v_q (complex128 [nq, n, n]), build_workspace, chi0_tau, chi0_omega, chi0_q (complex128),
+    ec_workspace (device tensors).  The tensors are kept alive with the batch, since the graph
+    holds their addresses."""
+
+    def __init__(self, ctx: Context, cells, nlanes: int):
+        import torch
+        f64 = torch.float64
+        self.ctx = ctx
+        self._keep = [cells]
+        arr = (_BatchCell * len(cells))()
+        self.nq = []
+        for k, c in enumerate(cells):
+            g, gp = _host(c["gamma_cos"], np.float64)
+            w, wp = _host(c["womega"], np.float64)
+            q, qp = _host(c["q_frac"], np.float64)
+            self._keep += [g, w, q]
+            cq = torch.view_as_real(c["chi0_q"]) if c["chi0_q"].dtype == torch.complex128 else c["chi0_q"]
+            vq = torch.view_as_real(c["v_q"]) if c["v_q"].dtype == torch.complex128 else c["v_q"]
+            bw, ew = c["build_workspace"], c["ec_workspace"]
+            arr[k] = _BatchCell(c["plan"].h, int(c["lane"]), int(w.shape[0]), int(q.shape[0]), float(c["spin_factor"]),
+                                gp, wp, qp, _dev(c["G_occ"], f64), _dev(c["G_un"], f64), _dev(c["C"], f64),
+                                _dev(vq, f64), _dev(bw), bw.numel() * bw.element_size(), _dev(c["chi0_tau"], f64),
+                                _dev(c["chi0_omega"], f64), _dev(cq, f64), _dev(ew), ew.numel() * ew.element_size())
+            self.nq.append(int(q.shape[0]))
+        h = ctypes.c_void_p()
+        ctx.check(ctx.lib.rpa_batch_create(ctx.h, len(cells), int(nlanes), arr, ctypes.byref(h)))
+        self.h = h
+        self.ncells = len(cells)
+        ctx._batches.add(self)
+
+    def run(self):
+        """One graph launch of every cell on the context's stream (asynchronous)."""
+        self.ctx.check(self.ctx.lib.rpa_batch_run(self.h))
+
+    def result(self):
+        """(E_c per cell, per-q terms of every cell concatenated); waits for the stream."""
+        ec = np.zeros(self.ncells)
+        ecq = np.zeros(sum(self.nq))
+        self.ctx.check(self.ctx.lib.rpa_batch_result(self.h, ec.ctypes.data_as(ctypes.c_void_p),
+                                                     ecq.ctypes.data_as(ctypes.c_void_p)))
+        return ec, ecq
+
+    def close(self):
+        if getattr(self, "h", None) and getattr(self.ctx, "h", None):
+            self.ctx.lib.rpa_batch_destroy(self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -173,6 +173,142 @@ int ec_default_batch(int n, int nq, int nomega) {
 
 // T: precision of G, N and the N stage; bf16: split-BF16 fused kernel (T = float).  G is rescaled
 // per tau by a power of two in the FP32 and BF16X3 paths.
+namespace {
+// Largest (q, omega) batch whose layout fits the workspace; false if even one matrix does not.
+bool ec_fit_layout(int n, int nq, int nomega, size_t workspace_bytes, EcLayout &out) {
+  const int total = nq * nomega;
+  int cw = std::min(total, std::max(1, ec_default_batch(n, nq, nomega)));
+  while (cw > 1 && ec_layout(n, nq, nomega, cw).total > workspace_bytes) cw = (cw + 1) / 2;
+  while (cw < total && ec_layout(n, nq, nomega, cw + 1).total <= workspace_bytes) ++cw;
+  out = ec_layout(n, nq, nomega, cw);
+  return out.total <= workspace_bytes;
+}
+
+// Status flags written by the energy stage: [nq] for the Cholesky of v(q), then
+// [nq][nomega] for 1 - L^H chi L (1: not positive definite, 2: non-finite log-determinant).
+int ec_check_flags(rpa_ctx *ctx, const int *hflags, int nq, int nomega, const std::string &where) {
+  for (int q = 0; q < nq; ++q)
+    if (hflags[q])
+      return fail(ctx, RPA_ERR_NOT_HPD, where + "v(q) is not Hermitian positive definite at q index " + std::to_string(q));
+  for (int q = 0; q < nq; ++q)
+    for (int k = 0; k < nomega; ++k) {
+      const int fl = hflags[nq + q * nomega + k];
+      if (fl == 1)
+        return fail(ctx, RPA_ERR_NOT_HPD, where + "1 - L^H chi L is not positive definite at q index " +
+                                              std::to_string(q) + ", omega index " + std::to_string(k));
+      if (fl == 2)
+        return fail(ctx, RPA_ERR_NONFINITE, where + "non-finite log-determinant at q index " + std::to_string(q) +
+                                                ", omega index " + std::to_string(k));
+    }
+  return RPA_OK;
+}
+
+// The energy stage of one cell enqueued on stream s: kernels only (no host copy, no wait, no
+// memset), so it can be captured into a graph.  womega_dev: device [nomega].  Leaves the flags
+// and per-q terms (ecq[q], ecq[nq] = E_c) in the workspace at l.flags and l.ecq.
+int ec_enqueue(rpa_ctx *ctx, hipStream_t s, int n, int nq, int nomega, const double *womega_dev,
+               const double *chi0_q, const double *v_q, char *ws, const EcLayout &l) {
+  const int total = nq * nomega, cw = l.cw;
+  double *L = (double *)(ws + l.L), *T = (double *)(ws + l.T), *B = (double *)(ws + l.B),
+         *W = (double *)(ws + l.W), *trB = (double *)(ws + l.trB), *f = (double *)(ws + l.f),
+         *ecq = (double *)(ws + l.ecq);
+  int *flags = (int *)(ws + l.flags);
+  const size_t mat = (size_t)n * n * 2;   // doubles per complex matrix
+  HIP_TRY(ctx, launch_fill_int(flags, (size_t)(nq + nq * nomega), 0, s));
+  // v(q) = L_q L_q^H for every q at once
+  HIP_TRY(ctx, launch_copy_words(L, v_q, nq * mat * 2, s));
+  HIP_TRY(ctx, launch_cholesky(L, mat, n, nq, W, flags, 0, s));
+  HIP_TRY(ctx, launch_zero_upper(L, mat, n, nq, s));
+  // (q, omega) pairs g = q * nomega + omega in batches of cw
+  for (int b0 = 0; b0 < total; b0 += cw) {
+    const int nb = std::min(cw, total - b0);
+    // T = chi(q, omega) L_q   (L_q lower triangular: k >= first column of the tile)
+    ZgemmArgs g{};
+    g.M = g.N = g.K = n;
+    g.A = chi0_q;
+    g.lda = n;
+    g.outerA = (long long)mat;                 // q
+    g.innerA = (long long)nq * mat;            // omega
+    g.opA = 0;
+    g.B = L;
+    g.ldb = n;
+    g.outerB = (long long)mat;
+    g.opB = 0;
+    g.C = T;
+    g.ldc = n;
+    g.strideC = (long long)mat;
+    g.boff = b0;
+    g.binner = nomega;
+    g.alpha = 1.0;
+    g.kmode = 1;
+    HIP_TRY(ctx, launch_zgemm(g, nb, s));
+    // B = L_q^H T, lower triangle (L^H upper triangular: k >= first row of the tile)
+    ZgemmArgs h{};
+    h.M = h.N = h.K = n;
+    h.A = L;
+    h.lda = n;
+    h.outerA = (long long)mat;
+    h.opA = 1;
+    h.B = T;
+    h.ldb = n;
+    h.strideB = (long long)mat;
+    h.opB = 0;
+    h.C = B;
+    h.ldc = n;
+    h.strideC = (long long)mat;
+    h.boff = b0;
+    h.binner = nomega;
+    h.alpha = 1.0;
+    h.lower_only = 1;
+    h.kmode = 2;
+    HIP_TRY(ctx, launch_zgemm(h, nb, s));
+    HIP_TRY(ctx, launch_trace_identity_minus(B, mat, n, nb, trB + b0, s));
+    HIP_TRY(ctx, launch_cholesky(B, mat, n, nb, W, flags, nq + b0, s));
+    HIP_TRY(ctx, launch_logdet(B, mat, n, nb, trB + b0, f + b0, flags, nq + b0, s));
+  }
+  HIP_TRY(ctx, launch_quadrature(f, womega_dev, nq, nomega, ecq, s));
+  return RPA_OK;
+}
+
+// phases exp(2 pi i q . n_R) for R -> q, the fractional part of q . n_R reduced before the 2 pi
+std::vector<double> r2q_phases(const int mesh[3], int nq, const double *q_frac) {
+  const int nR = mesh[0] * mesh[1] * mesh[2];
+  std::vector<double> ph((size_t)2 * nq * nR);
+  for (int q = 0; q < nq; ++q)
+    for (int r = 0; r < nR; ++r) {
+      const int n0 = r / (mesh[1] * mesh[2]), n1 = (r / mesh[2]) % mesh[1], n2 = r % mesh[2];
+      double x = q_frac[3 * q] * n0 + q_frac[3 * q + 1] * n1 + q_frac[3 * q + 2] * n2;
+      x -= std::floor(x);
+      ph[((size_t)q * nR + r) * 2] = std::cos(2.0 * M_PI * x);
+      ph[((size_t)q * nR + r) * 2 + 1] = std::sin(2.0 * M_PI * x);
+    }
+  return ph;
+}
+}  // namespace
+
+// ---- batches of cells ----
+struct BatchCell {
+  rpa_batch_cell io;
+  int n = 0, ntau = 0, nR = 0;
+  size_t off_gamma = 0, off_ph = 0, off_w = 0;   // doubles into the batch's parameter buffer
+  size_t off_flags = 0, off_ecq = 0;             // bytes into the batch's result buffer
+  EcLayout el{};
+};
+
+struct rpa_batch {
+  rpa_ctx *ctx = nullptr;
+  int nlanes = 0;
+  std::vector<BatchCell> cells;
+  std::vector<hipStream_t> lanes;
+  hipStream_t origin = nullptr;                  // the stream the graph is captured on
+  std::vector<hipEvent_t> events;                // fork, then one join per lane
+  double *dparams = nullptr;
+  char *dres = nullptr;
+  size_t res_bytes = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
 template <typename T>
 static int build_impl(rpa_plan *p, const double *G_occ, const double *G_un, const double *C, char *ws, double negs,
                       double *chi0_tau, bool bf16) {
@@ -622,16 +758,7 @@ int chi0_R_to_q(rpa_ctx *ctx, const int mesh[3], int nbatch, size_t m, int nq, c
   if ((size_t)2 * nq * nR * sizeof(double) > 64 * 1024)
     return fail(ctx, RPA_ERR_UNSUPPORTED, "nq * nR must not exceed 4096");
   if (m == 0) return RPA_OK;
-  // phases exp(2 pi i q . n_R), the fractional part of q . n_R reduced before the 2 pi
-  std::vector<double> ph((size_t)2 * nq * nR);
-  for (int q = 0; q < nq; ++q)
-    for (int r = 0; r < nR; ++r) {
-      const int n0 = r / (mesh[1] * mesh[2]), n1 = (r / mesh[2]) % mesh[1], n2 = r % mesh[2];
-      double x = q_frac[3 * q] * n0 + q_frac[3 * q + 1] * n1 + q_frac[3 * q + 2] * n2;
-      x -= std::floor(x);
-      ph[((size_t)q * nR + r) * 2] = std::cos(2.0 * M_PI * x);
-      ph[((size_t)q * nR + r) * 2 + 1] = std::sin(2.0 * M_PI * x);
-    }
+  const std::vector<double> ph = r2q_phases(mesh, nq, q_frac);
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   HIP_TRY(ctx, hipMemcpyAsync(ctx->params, ph.data(), ph.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
   Timed tm(ctx, "r2q");
@@ -650,97 +777,209 @@ int rpa_correlation_energy(rpa_ctx *ctx, int n, int nq, int nomega, const double
   if (!ctx) return RPA_ERR_ARG;
   if (!womega || !chi0_q || !v_q || !workspace || !Ec) return fail(ctx, RPA_ERR_ARG, "null pointer");
   if (n <= 0 || nq <= 0 || nomega <= 0) return fail(ctx, RPA_ERR_ARG, "sizes must be positive");
-  const int total = nq * nomega;
-  int cw = std::min(total, std::max(1, ec_default_batch(n, nq, nomega)));
-  while (cw > 1 && ec_layout(n, nq, nomega, cw).total > workspace_bytes) cw = (cw + 1) / 2;
-  while (cw < total && ec_layout(n, nq, nomega, cw + 1).total <= workspace_bytes) ++cw;
-  const EcLayout l = ec_layout(n, nq, nomega, cw);
-  if (l.total > workspace_bytes)
+  EcLayout l;
+  if (!ec_fit_layout(n, nq, nomega, workspace_bytes, l))
     return fail(ctx, RPA_ERR_WORKSPACE, "workspace smaller than rpa_ec_workspace_size with one matrix per batch");
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   hipStream_t s = ctx->stream;
   char *ws = (char *)workspace;
-  double *L = (double *)(ws + l.L), *T = (double *)(ws + l.T), *B = (double *)(ws + l.B),
-         *W = (double *)(ws + l.W), *trB = (double *)(ws + l.trB), *f = (double *)(ws + l.f),
-         *ecq = (double *)(ws + l.ecq), *wdev = (double *)(ws + l.w);
-  int *flags = (int *)(ws + l.flags);
-  const size_t mat = (size_t)n * n * 2;   // doubles per complex matrix
-  std::unique_ptr<Timed> tm(new Timed(ctx, "ec_stage"));   // closed after the quadrature
-  HIP_TRY(ctx, launch_fill_int(flags, (size_t)(nq + nq * nomega), 0, s));
+  double *wdev = (double *)(ws + l.w);
   HIP_TRY(ctx, hipMemcpyAsync(wdev, womega, nomega * 8, hipMemcpyHostToDevice, s));
-  // v(q) = L_q L_q^H for every q at once
-  HIP_TRY(ctx, hipMemcpyAsync(L, v_q, nq * mat * 8, hipMemcpyDeviceToDevice, s));
-  HIP_TRY(ctx, launch_cholesky(L, mat, n, nq, W, flags, 0, s));
-  HIP_TRY(ctx, launch_zero_upper(L, mat, n, nq, s));
-  // (q, omega) pairs g = q * nomega + omega in batches of cw
-  for (int b0 = 0; b0 < total; b0 += cw) {
-    const int nb = std::min(cw, total - b0);
-    // T = chi(q, omega) L_q   (L_q lower triangular: k >= first column of the tile)
-    ZgemmArgs g{};
-    g.M = g.N = g.K = n;
-    g.A = chi0_q;
-    g.lda = n;
-    g.outerA = (long long)mat;                 // q
-    g.innerA = (long long)nq * mat;            // omega
-    g.opA = 0;
-    g.B = L;
-    g.ldb = n;
-    g.outerB = (long long)mat;
-    g.opB = 0;
-    g.C = T;
-    g.ldc = n;
-    g.strideC = (long long)mat;
-    g.boff = b0;
-    g.binner = nomega;
-    g.alpha = 1.0;
-    g.kmode = 1;
-    HIP_TRY(ctx, launch_zgemm(g, nb, s));
-    // B = L_q^H T, lower triangle (L^H upper triangular: k >= first row of the tile)
-    ZgemmArgs h{};
-    h.M = h.N = h.K = n;
-    h.A = L;
-    h.lda = n;
-    h.outerA = (long long)mat;
-    h.opA = 1;
-    h.B = T;
-    h.ldb = n;
-    h.strideB = (long long)mat;
-    h.opB = 0;
-    h.C = B;
-    h.ldc = n;
-    h.strideC = (long long)mat;
-    h.boff = b0;
-    h.binner = nomega;
-    h.alpha = 1.0;
-    h.lower_only = 1;
-    h.kmode = 2;
-    HIP_TRY(ctx, launch_zgemm(h, nb, s));
-    HIP_TRY(ctx, launch_trace_identity_minus(B, mat, n, nb, trB + b0, s));
-    HIP_TRY(ctx, launch_cholesky(B, mat, n, nb, W, flags, nq + b0, s));
-    HIP_TRY(ctx, launch_logdet(B, mat, n, nb, trB + b0, f + b0, flags, nq + b0, s));
+  {
+    Timed tm(ctx, "ec_stage");
+    const int rc = ec_enqueue(ctx, s, n, nq, nomega, wdev, chi0_q, v_q, ws, l);
+    if (rc != RPA_OK) return rc;
   }
-  HIP_TRY(ctx, launch_quadrature(f, wdev, nq, nomega, ecq, s));
-  tm.reset();
   std::vector<int> hflags(nq + nq * nomega);
   std::vector<double> hecq(nq + 1);
-  HIP_TRY(ctx, hipMemcpyAsync(hflags.data(), flags, hflags.size() * 4, hipMemcpyDeviceToHost, s));
-  HIP_TRY(ctx, hipMemcpyAsync(hecq.data(), ecq, hecq.size() * 8, hipMemcpyDeviceToHost, s));
+  HIP_TRY(ctx, hipMemcpyAsync(hflags.data(), ws + l.flags, hflags.size() * 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(ctx, hipMemcpyAsync(hecq.data(), ws + l.ecq, hecq.size() * 8, hipMemcpyDeviceToHost, s));
   HIP_TRY(ctx, hipStreamSynchronize(s));
-  for (int q = 0; q < nq; ++q)
-    if (hflags[q]) return fail(ctx, RPA_ERR_NOT_HPD, "v(q) is not Hermitian positive definite at q index " + std::to_string(q));
-  for (int q = 0; q < nq; ++q)
-    for (int k = 0; k < nomega; ++k) {
-      const int fl = hflags[nq + q * nomega + k];
-      if (fl == 1)
-        return fail(ctx, RPA_ERR_NOT_HPD, "1 - L^H chi L is not positive definite at q index " + std::to_string(q) +
-                                              ", omega index " + std::to_string(k));
-      if (fl == 2)
-        return fail(ctx, RPA_ERR_NONFINITE, "non-finite log-determinant at q index " + std::to_string(q) +
-                                                ", omega index " + std::to_string(k));
-    }
+  const int rc = ec_check_flags(ctx, hflags.data(), nq, nomega, "");
+  if (rc != RPA_OK) return rc;
   *Ec = hecq[nq];
   if (Ec_q)
     for (int q = 0; q < nq; ++q) Ec_q[q] = hecq[q];
+  return RPA_OK;
+}
+
+static void batch_release(rpa_batch *b) {
+  if (!b) return;
+  hipSetDevice(b->ctx->device);
+  hipDeviceSynchronize();
+  if (b->exec) hipGraphExecDestroy(b->exec);
+  if (b->graph) hipGraphDestroy(b->graph);
+  for (hipEvent_t e : b->events) hipEventDestroy(e);
+  for (hipStream_t st : b->lanes) hipStreamDestroy(st);
+  if (b->origin) hipStreamDestroy(b->origin);
+  if (b->dparams) hipFree(b->dparams);
+  if (b->dres) hipFree(b->dres);
+  delete b;
+}
+
+// The whole path of one cell enqueued on stream s (the context's stream is pointed at s
+// meanwhile); kernels only.
+static int batch_enqueue_cell(rpa_batch *b, const BatchCell &c, hipStream_t s) {
+  rpa_ctx *ctx = b->ctx;
+  rpa_plan *p = c.io.plan;
+  ctx->stream = s;
+  char *bws = (char *)c.io.build_workspace;
+  const double negs = -c.io.spin_factor;
+  int rc = p->prec == RPA_FP64
+               ? build_impl<double>(p, c.io.G_occ, c.io.G_un, c.io.C, bws, negs, c.io.chi0_tau, false)
+               : build_impl<float>(p, c.io.G_occ, c.io.G_un, c.io.C, bws, negs, c.io.chi0_tau, p->prec == RPA_BF16X3);
+  if (rc != RPA_OK) return rc;
+  const size_t n2 = (size_t)c.n * c.n;
+  HIP_TRY(ctx, launch_cos_transform(b->dparams + c.off_gamma, c.ntau, c.io.nomega, (size_t)c.nR * n2, c.io.chi0_tau,
+                                    c.io.chi0_omega, s));
+  HIP_TRY(ctx, launch_r2q(b->dparams + c.off_ph, c.nR, c.io.nq, c.io.nomega, n2, c.io.chi0_omega, c.io.chi0_q, s));
+  char *ews = (char *)c.io.ec_workspace;
+  rc = ec_enqueue(ctx, s, c.n, c.io.nq, c.io.nomega, b->dparams + c.off_w, c.io.chi0_q, c.io.v_q, ews, c.el);
+  if (rc != RPA_OK) return rc;
+  HIP_TRY(ctx, launch_copy_words(b->dres + c.off_flags, ews + c.el.flags, (size_t)c.io.nq * (1 + c.io.nomega), s));
+  HIP_TRY(ctx, launch_copy_words(b->dres + c.off_ecq, ews + c.el.ecq, (size_t)2 * (c.io.nq + 1), s));
+  return RPA_OK;
+}
+
+int rpa_batch_create(rpa_ctx *ctx, int ncells, int nlanes, const rpa_batch_cell *cells, rpa_batch **out) {
+  if (!ctx) return RPA_ERR_ARG;
+  if (!out || !cells) return fail(ctx, RPA_ERR_ARG, "null argument");
+  *out = nullptr;
+  if (ncells <= 0 || nlanes <= 0 || nlanes > 64) return fail(ctx, RPA_ERR_ARG, "need ncells > 0 and 1 <= nlanes <= 64");
+  std::vector<BatchCell> bc(ncells);
+  std::vector<double> params;
+  size_t res = 0;
+  auto pad = [&]() { params.resize((params.size() + 31) / 32 * 32, 0.0); };
+  for (int i = 0; i < ncells; ++i) {
+    const rpa_batch_cell &io = cells[i];
+    const std::string at = "cell " + std::to_string(i) + ": ";
+    if (!io.plan || io.plan->ctx != ctx) return fail(ctx, RPA_ERR_ARG, at + "plan missing or of another context");
+    if (io.lane < 0 || io.lane >= nlanes) return fail(ctx, RPA_ERR_ARG, at + "lane out of range");
+    if (!io.gamma_cos || !io.womega || !io.q_frac || !io.G_occ || !io.G_un || !io.v_q || !io.build_workspace ||
+        !io.chi0_tau || !io.chi0_omega || !io.chi0_q || !io.ec_workspace || (io.plan->nblk > 0 && !io.C))
+      return fail(ctx, RPA_ERR_ARG, at + "null pointer");
+    if (io.nomega <= 0 || io.nomega > 64 || io.nq <= 0) return fail(ctx, RPA_ERR_ARG, at + "nomega in [1, 64], nq > 0");
+    BatchCell &c = bc[i];
+    c.io = io;
+    c.n = io.plan->nauxtot;
+    c.ntau = io.plan->ntau;
+    c.nR = io.plan->nR;
+    if ((size_t)2 * io.nq * c.nR * sizeof(double) > 64 * 1024)
+      return fail(ctx, RPA_ERR_UNSUPPORTED, at + "nq * nR must not exceed 4096");
+    if (io.build_workspace_bytes < io.plan->ws_total)
+      return fail(ctx, RPA_ERR_WORKSPACE, at + "build workspace smaller than the plan's");
+    if (!ec_fit_layout(c.n, io.nq, io.nomega, io.ec_workspace_bytes, c.el))
+      return fail(ctx, RPA_ERR_WORKSPACE, at + "energy workspace too small");
+    pad();
+    c.off_gamma = params.size();
+    params.insert(params.end(), io.gamma_cos, io.gamma_cos + (size_t)io.nomega * c.ntau);
+    pad();
+    c.off_ph = params.size();
+    const std::vector<double> ph = r2q_phases(io.plan->mesh, io.nq, io.q_frac);
+    params.insert(params.end(), ph.begin(), ph.end());
+    pad();
+    c.off_w = params.size();
+    params.insert(params.end(), io.womega, io.womega + io.nomega);
+    c.off_flags = res;
+    res = align_up(res + (size_t)io.nq * (1 + io.nomega) * sizeof(int));
+    c.off_ecq = res;
+    res = align_up(res + (size_t)(io.nq + 1) * sizeof(double));
+  }
+  pad();
+  rpa_batch *b = new rpa_batch();
+  b->ctx = ctx;
+  b->nlanes = nlanes;
+  b->cells = bc;
+  b->res_bytes = res;
+  auto bail = [&](int code, const std::string &msg) {
+    batch_release(b);
+    return fail(ctx, code, msg);
+  };
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e == hipSuccess) e = hipMalloc(&b->dparams, params.size() * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&b->dres, res);
+  if (e == hipSuccess) e = hipMemcpy(b->dparams, params.data(), params.size() * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->origin, hipStreamNonBlocking);
+  for (int l = 0; l < nlanes && e == hipSuccess; ++l) {
+    hipStream_t st = nullptr;
+    e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e == hipSuccess) b->lanes.push_back(st);
+  }
+  for (int k = 0; k <= nlanes && e == hipSuccess; ++k) {
+    hipEvent_t ev = nullptr;
+    e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e == hipSuccess) b->events.push_back(ev);
+  }
+  if (e != hipSuccess) return bail(RPA_ERR_HIP, std::string("batch setup: ") + hipGetErrorString(e));
+
+  // capture: fork every lane off the origin stream, enqueue the cells, join
+  e = hipStreamBeginCapture(b->origin, hipStreamCaptureModeRelaxed);
+  if (e != hipSuccess) return bail(RPA_ERR_HIP, std::string("begin capture: ") + hipGetErrorString(e));
+  const hipStream_t saved_stream = ctx->stream;
+  const bool saved_profile = ctx->profile;
+  ctx->profile = false;
+  int rc = RPA_OK;
+  e = hipEventRecord(b->events[0], b->origin);
+  for (int l = 0; l < nlanes && e == hipSuccess; ++l) e = hipStreamWaitEvent(b->lanes[l], b->events[0], 0);
+  if (e != hipSuccess) rc = fail(ctx, RPA_ERR_HIP, std::string("batch fork: ") + hipGetErrorString(e));
+  for (int i = 0; i < ncells && rc == RPA_OK; ++i) {
+    rc = batch_enqueue_cell(b, b->cells[i], b->lanes[b->cells[i].io.lane]);
+    if (rc != RPA_OK) ctx->err = "cell " + std::to_string(i) + ": " + ctx->err;
+  }
+  ctx->stream = saved_stream;
+  ctx->profile = saved_profile;
+  for (int l = 0; l < nlanes && rc == RPA_OK; ++l) {
+    e = hipEventRecord(b->events[1 + l], b->lanes[l]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b->origin, b->events[1 + l], 0);
+    if (e != hipSuccess) rc = fail(ctx, RPA_ERR_HIP, std::string("batch join: ") + hipGetErrorString(e));
+  }
+  const hipError_t ee = hipStreamEndCapture(b->origin, &b->graph);
+  if (rc != RPA_OK) {
+    const std::string msg = ctx->err;
+    batch_release(b);
+    return fail(ctx, rc, msg);
+  }
+  if (ee != hipSuccess) return bail(RPA_ERR_HIP, std::string("end capture: ") + hipGetErrorString(ee));
+  e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) return bail(RPA_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+  *out = b;
+  return RPA_OK;
+}
+
+int rpa_batch_run(rpa_batch *b) {
+  if (!b) return RPA_ERR_ARG;
+  rpa_ctx *ctx = b->ctx;
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  HIP_TRY(ctx, hipGraphLaunch(b->exec, ctx->stream));
+  return RPA_OK;
+}
+
+int rpa_batch_result(rpa_batch *b, double *Ec, double *Ec_q) {
+  if (!b) return RPA_ERR_ARG;
+  rpa_ctx *ctx = b->ctx;
+  if (!Ec) return fail(ctx, RPA_ERR_ARG, "null pointer");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  std::vector<char> h(b->res_bytes);
+  HIP_TRY(ctx, hipMemcpyAsync(h.data(), b->dres, b->res_bytes, hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  size_t qo = 0;
+  for (size_t i = 0; i < b->cells.size(); ++i) {
+    const BatchCell &c = b->cells[i];
+    const int rc = ec_check_flags(ctx, (const int *)(h.data() + c.off_flags), c.io.nq, c.io.nomega,
+                                  "cell " + std::to_string(i) + ": ");
+    if (rc != RPA_OK) return rc;
+    const double *ecq = (const double *)(h.data() + c.off_ecq);
+    Ec[i] = ecq[c.io.nq];
+    if (Ec_q)
+      for (int q = 0; q < c.io.nq; ++q) Ec_q[qo + q] = ecq[q];
+    qo += c.io.nq;
+  }
+  return RPA_OK;
+}
+
+int rpa_batch_destroy(rpa_batch *b) {
+  if (!b) return RPA_ERR_ARG;
+  batch_release(b);
   return RPA_OK;
 }
 

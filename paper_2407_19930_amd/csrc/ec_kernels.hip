@@ -332,11 +332,32 @@ __global__ void fill_int_kernel(int *p, size_t n, int v) {
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) p[e] = v;
 }
 
+// plain copy of n 4-byte words (16-byte vectors when both ends allow it); a kernel rather than
+// a memcpy so that captured graphs hold kernel nodes only
+__global__ void copy_words_kernel(unsigned *__restrict__ dst, const unsigned *__restrict__ src, size_t n) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (((reinterpret_cast<uintptr_t>(dst) | reinterpret_cast<uintptr_t>(src)) & 15) == 0) {
+    const size_t n4 = n / 4;
+    for (size_t e = t; e < n4; e += stride) reinterpret_cast<uint4 *>(dst)[e] = reinterpret_cast<const uint4 *>(src)[e];
+    for (size_t e = 4 * n4 + t; e < n; e += stride) dst[e] = src[e];
+  } else {
+    for (size_t e = t; e < n; e += stride) dst[e] = src[e];
+  }
+}
+
 }  // namespace
 
 hipError_t launch_fill_int(int *p, size_t n, int v, hipStream_t s) {
   const int blocks = (int)std::min<size_t>((n + 255) / 256, 1024);
   hipLaunchKernelGGL(fill_int_kernel, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_words(void *dst, const void *src, size_t nwords, hipStream_t s) {
+  if (nwords == 0) return hipSuccess;
+  const int blocks = (int)std::min<size_t>((nwords / 4 + 255) / 256 + 1, 4096);
+  hipLaunchKernelGGL(copy_words_kernel, dim3(blocks), dim3(256), 0, s, (unsigned *)dst, (const unsigned *)src, nwords);
   return hipGetLastError();
 }
 

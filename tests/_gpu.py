@@ -52,5 +52,16 @@ def gpu_pipeline(inp, precision="fp64", ctx=None):
                 plan=plan)
 
 
+def batch_cell(inp, dev_in=None):
+    """Per-cell dict for paper_2407_19930_amd.batching.make_batch from a seeded input bundle."""
+    import torch
+    d = dev_in or device_inputs(inp)
+    b = inp.blocks
+    return dict(nao=inp.nao, naux=inp.naux, mesh=inp.cell.mesh, blk_I=b.I, blk_K=b.K, blk_R=b.R, blk_off=b.off,
+                ntau=inp.ntau, spin_factor=inp.spin_factor, gamma_cos=inp.gamma_cos, womega=inp.womega,
+                q_frac=inp.kfrac, G_occ=d["Gocc"], G_un=d["Gun"], C=d["C"],
+                v_q=torch.from_numpy(inp.vq).to("cuda"))
+
+
 def rel(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(np.asarray(b)), 1e-300))
