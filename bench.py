@@ -46,7 +46,11 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3", "fp64"])
     ap.add_argument("--workload", type=int, default=1,
-                    help="workload index (1: 8-atom diamond-like cell, 2: 32-atom two-species cell)")
+                    help="workload index (1: 8-atom diamond-like cell, 2: 32-atom two-species cell, "
+                         "4: 64 serving cells in one graph)")
+    ap.add_argument("--lanes", type=int, default=4, help="concurrent lanes of the serving batch (workload 4)")
+    ap.add_argument("--gen-workers", type=int, default=16, help="processes generating the serving cells")
+    ap.add_argument("--ncells", type=int, default=64, help="serving cells used (workload 4; the first n of 64)")
     ap.add_argument("--no-fp64-check", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
@@ -111,8 +115,109 @@ def cpu_baseline(inp, budget_s):
                       "Algorithm 1; %.1f s, %.3g algorithmic flops" % (nblk, dt, flops)}
 
 
+def _gen_cell(cell):
+    from threadpoolctl import threadpool_limits
+    from rpa_synth import make_inputs
+    with threadpool_limits(1):
+        return make_inputs(cell)
+
+
+def serving_main(args):
+    """Workload 4: 64 independent cells (2-16 atoms, k-meshes 1/8/27, 8-16 tau), the whole path
+    of every cell in one captured graph; one step = one graph launch plus the result read."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    import torch
+    from paper_2407_19930_amd import Context
+    from paper_2407_19930_amd.batching import make_batch
+    from rpa_synth.configs import serving_cells
+    cells = serving_cells()[:args.ncells]
+    dev = "cuda"
+    t0 = time.perf_counter()
+    io, natoms, names = [], [], []
+    with cf.ProcessPoolExecutor(max_workers=max(1, args.gen_workers), mp_context=mp.get_context("fork")) as ex:
+        for k, inp in enumerate(ex.map(_gen_cell, cells)):
+            b = inp.blocks
+            io.append(dict(nao=inp.nao, naux=inp.naux, mesh=inp.cell.mesh, blk_I=b.I, blk_K=b.K, blk_R=b.R,
+                           blk_off=b.off, ntau=inp.ntau, spin_factor=inp.spin_factor, gamma_cos=inp.gamma_cos,
+                           womega=inp.womega, q_frac=inp.kfrac, G_occ=torch.from_numpy(inp.Gocc).to(dev),
+                           G_un=torch.from_numpy(inp.Gun).to(dev), C=torch.from_numpy(b.C).to(dev),
+                           v_q=torch.from_numpy(inp.vq).to(dev)))
+            natoms.append(inp.natoms)
+            names.append(inp.cell.name)
+            del inp
+            log("cell %d/%d ready (%.0f s)" % (k + 1, len(cells), time.perf_counter() - t0))
+    gen_s = time.perf_counter() - t0
+    natoms = np.array(natoms)
+    ctx = Context(0)
+    extra = {}
+    ec64 = None
+    if not args.no_fp64_check and args.precision != "fp64":
+        t0 = time.perf_counter()
+        b64, _, _ = make_batch(ctx, io, args.lanes, "fp64")
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        b64.run()
+        ec64, _ = b64.result()
+        extra["fp64_ms_per_step"] = (time.perf_counter() - t1) * 1e3
+        log("fp64 reference batch: capture %.1f s, run %.2f s" % (t1 - t0, extra["fp64_ms_per_step"] / 1e3))
+        b64.close()
+        del b64
+        torch.cuda.empty_cache()
+    t0 = time.perf_counter()
+    batch, plans, lanes = make_batch(ctx, io, args.lanes, args.precision)
+    torch.cuda.synchronize()
+    capture_s = time.perf_counter() - t0
+    log("batch of %d cells in %d lanes captured in %.1f s" % (len(io), args.lanes, capture_s))
+    alg = sum(p.flops()[0] for p in plans)
+    for i in range(args.warmup):
+        batch.run()
+        batch.result()
+        log("warmup step %d done" % i)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        batch.run()
+        ec, _ = batch.result()
+        log("timed step %d done" % i)
+    dt = (time.perf_counter() - t0) / args.steps
+    if ec64 is not None:
+        d = np.abs(ec - ec64) / natoms
+        extra["max_dEc_per_atom_vs_fp64"] = float(d.max())
+        extra["worst_cell"] = names[int(d.argmax())]
+        extra["speedup_vs_fp64"] = extra["fp64_ms_per_step"] / (dt * 1e3)
+    rec = {
+        "metric": "chi0(R,tau) build TFLOP/s + E_c time, mixed vs FP64 at |dE_c| <= 1e-6 Ha/atom",
+        "value": alg / dt / 1e12,
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.precision,
+        "data": "synthetic",
+        "config": {"workload": "serving: %d cells of 2-16 atoms (%d atoms), k-meshes 1/8/27, 8-16 tau, rcut 8 A, "
+                               "one graph launch, %d lanes" % (len(io), int(natoms.sum()), args.lanes),
+                   "ncells": len(io), "natoms_total": int(natoms.sum()), "lanes": args.lanes},
+        "roofline": None,
+        "cpu_baseline": None,
+        "cells_per_s": len(io) / dt,
+        "alg_tflop_per_step": alg / 1e12,
+        "capture_s": capture_s,
+        "input_generation_s": gen_s,
+        "Ec_per_atom_range": [float((ec / natoms).min()), float((ec / natoms).max())],
+    }
+    rec.update(extra)
+    print(json.dumps(rec))
+
+
 def main():
     args = parse()
+    if args.workload == 4 and args.gpus == 1:
+        return serving_main(args)
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the path is measured on one MI355X "
               "(multi-GPU sharding is a design note only); use --gpus 1", file=sys.stderr)
