@@ -172,12 +172,22 @@ def coulomb(cell: Cell, nauxtot, nq):
         L = (rng.standard_normal((nauxtot, nauxtot)) + 1j * rng.standard_normal((nauxtot, nauxtot))) * np.sqrt(0.5)
         v = L @ L.conj().T + 1e-3 * np.eye(nauxtot)
         v = 0.5 * (v + v.conj().T)
-        lmax = np.linalg.eigvalsh(v)[-1]
-        vq[q] = v * (cell.v_scale / lmax)
+        vq[q] = v * (cell.v_scale / _lambda_max(v))
     return vq
 
 
-def make_inputs(cell: Cell, with_coulomb=True, keep_wfc=True) -> Inputs:
+def _lambda_max(v):
+    """Largest eigenvalue of a Hermitian positive definite matrix: dense for small sizes,
+    Lanczos from a fixed start vector (deterministic) for large ones."""
+    n = v.shape[0]
+    if n <= 2048:
+        return float(np.linalg.eigvalsh(v)[-1])
+    from scipy.sparse.linalg import eigsh
+    return float(eigsh(v, k=1, which="LA", v0=np.ones(n, dtype=v.dtype), tol=1e-13,
+                       return_eigenvectors=False)[0])
+
+
+def make_inputs(cell: Cell, with_coulomb=True, keep_wfc=True, with_green=True) -> Inputs:
     I, K, R, d, margin = lat.neighbour_pairs(cell.lattice, cell.frac, cell.rcut)
     nao, naux = cell.nao, cell.naux
     nb, nauxtot = int(nao.sum()), int(naux.sum())
@@ -196,7 +206,7 @@ def make_inputs(cell: Cell, with_coulomb=True, keep_wfc=True) -> Inputs:
     emin = GAP
     emax = float(eps.max() - eps.min())
     g = make_grids(cell.ntau, emin, emax)
-    Gocc, Gun = green_functions(eps, wfc, nocc, mu, g["tau"], kfrac, Rvec)
+    Gocc, Gun = green_functions(eps, wfc, nocc, mu, g["tau"], kfrac, Rvec) if with_green else (None, None)
     blocks = lri_blocks(cell, I, K, R, d, margin)
     vq = coulomb(cell, nauxtot, len(kfrac)) if with_coulomb else None
     return Inputs(cell=cell, nao=nao, naux=naux, ao_off=lat.offsets(nao), aux_off=lat.offsets(naux),

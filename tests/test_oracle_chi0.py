@@ -151,3 +151,40 @@ def test_mutations_are_caught():
     finally:
         chi0.supercell_lri_tensor = orig_t
     assert rel(bad, sc) > 1e-3
+
+
+@pytest.mark.parametrize("spec", MICRO_SPECS)
+def test_bloch_form_equals_supercell_sum_over_states(spec):
+    """The Bloch-resolved product chi(q, i omega) x (used for the spectral radius of chi v, which
+    sets the Coulomb scale of the workloads) against the dense supercell sum over states taken
+    to q, at every q of the mesh."""
+    inp = micro(**spec)
+    w = float(np.min(inp.omega))
+    dense = fourier_R_to_q(aw.chi0_aw_omega(inp, [w]), inp.Rvec, inp.kfrac)[0]
+    rng = np.random.default_rng(3)
+    A = aw.bloch_c_all(inp)
+    for iq in range(len(inp.kfrac)):
+        x = rng.standard_normal(inp.nauxtot) + 1j * rng.standard_normal(inp.nauxtot)
+        assert rel(aw.BlochChi(inp, iq, w, A)(x), dense[iq] @ x) < 1e-12
+
+
+def test_bloch_form_catches_a_wrong_phase():
+    inp = micro(**MICRO_SPECS[0])             # 3x2x1 mesh: the phases matter
+    w = float(np.min(inp.omega))
+    dense = fourier_R_to_q(aw.chi0_aw_omega(inp, [w]), inp.Rvec, inp.kfrac)[0]
+    A = aw.bloch_c_all(inp)
+    A = [a.conj() for a in A]                                  # e^{-2 pi i k.R1}: the wrong phase
+    x = np.random.default_rng(4).standard_normal(inp.nauxtot).astype(np.complex128)
+    assert max(rel(aw.BlochChi(inp, iq, w, A)(x), dense[iq] @ x) for iq in range(len(inp.kfrac))) > 1e-3
+
+
+def test_spectral_radius_matches_dense_eigenvalues():
+    """Lanczos on L^H chi L against the eigenvalues of the dense chi(q, i omega_1) v(q) of the
+    tiny workload, whose Coulomb scale puts the maximum at 0.9."""
+    inp = cfg(0)
+    w = float(np.min(inp.omega))
+    dense = fourier_R_to_q(aw.chi0_aw_omega(inp, [w]), inp.Rvec, inp.kfrac)[0]
+    rho_dense = max(np.max(np.abs(np.linalg.eigvals(dense[q] @ inp.vq[q]))) for q in range(len(inp.kfrac)))
+    rho, _ = aw.spectral_radius_chi_v(inp)
+    assert abs(rho - rho_dense) <= 1e-9 * rho_dense
+    assert abs(rho - 0.9) < 1e-3
