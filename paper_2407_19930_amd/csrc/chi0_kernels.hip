@@ -118,8 +118,9 @@ __global__ __launch_bounds__(256) void pad_g_kernel(const double *__restrict__ G
 // Each thread loads, per contraction row, 8 consecutive elements of A and of B with 16-byte
 // vector loads.  128x128 output tile, 4 waves of 64x64 (16x16x4 MFMA), K step BK, LDS
 // double buffer with a padded row stride (conflict-free MFMA operand reads).
-// kSplit (available, not used by the FP32 path): FP32 partial sums added into FP64 every 256
-// contraction rows.
+// kSplit: the partial sums of every 256 contraction rows are added into a second accumulator
+// of type A2 (rounding error growing with sqrt(256) + sqrt(S/256) instead of sqrt(S) for S
+// contraction rows); not used by the launchers, since its registers halve the occupancy.
 // ---------------------------------------------------------------------------
 constexpr int NS_BM = 128, NS_BN = 128, NS_THREADS = 256;
 
@@ -127,7 +128,7 @@ template <typename T> struct alignas(16) Vec16 {
   T v[16 / sizeof(T)];
 };
 
-template <typename T, bool kSplit, int BK>
+template <typename T, bool kSplit, int BK, typename A2>
 __global__ __launch_bounds__(NS_THREADS) void nstage_kernel(Chi0Tables tb, NTiles tiles, const T *__restrict__ Gp,
                                                             const T *__restrict__ Cp, T *__restrict__ Nbuf) {
   typedef typename Mfma<T>::acc Acc;
@@ -212,7 +213,7 @@ __global__ __launch_bounds__(NS_THREADS) void nstage_kernel(Chi0Tables tb, NTile
   };
 
   Acc acc[4][4];
-  double acc64[4][4][4];
+  A2 acc64[4][4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -249,7 +250,7 @@ __global__ __launch_bounds__(NS_THREADS) void nstage_kernel(Chi0Tables tb, NTile
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
 #pragma unroll
-          for (int r = 0; r < 4; ++r) acc64[a][b][r] += (double)acc[a][b][r];
+          for (int r = 0; r < 4; ++r) acc64[a][b][r] += (A2)acc[a][b][r];
           acc[a][b] = Mfma<T>::zero();
         }
     }
@@ -578,13 +579,15 @@ hipError_t launch_nstage(const Chi0Tables &tb, const NTiles &tiles, const T *Gp,
                          hipStream_t s) {
   if (tiles.count == 0) return hipSuccess;
   if (sizeof(T) == 4)
-    // plain FP32 accumulation over the contraction (about 5000 rows on the 8-atom cell): FP64
-    // side accumulators would cost occupancy for a 5x smaller N error that chi does not need
-    hipLaunchKernelGGL((nstage_kernel<T, false, 32>), dim3(tiles.count), dim3(NS_THREADS), 0, s, tb, tiles, Gp, Cp,
-                       Nbuf);
+    // plain FP32 accumulation over the contraction (about 5000 rows on the 8-atom cell): a
+    // second accumulator level (FP32 or FP64) needs 64 or 128 more registers per lane and
+    // halves the occupancy.  K step 16: 37 KB of LDS tiles let four workgroups share a CU
+    // (four waves per SIMD), 13% faster than K step 32 with two despite twice the barriers.
+    hipLaunchKernelGGL((nstage_kernel<T, false, 16, T>), dim3(tiles.count), dim3(NS_THREADS), 0, s, tb, tiles, Gp,
+                       Cp, Nbuf);
   else
-    hipLaunchKernelGGL((nstage_kernel<T, false, 16>), dim3(tiles.count), dim3(NS_THREADS), 0, s, tb, tiles, Gp, Cp,
-                       Nbuf);
+    hipLaunchKernelGGL((nstage_kernel<T, false, 16, T>), dim3(tiles.count), dim3(NS_THREADS), 0, s, tb, tiles, Gp,
+                       Cp, Nbuf);
   return hipGetLastError();
 }
 
