@@ -2,14 +2,9 @@
 serving workload (2-16 atoms, k-meshes 1 and 2, 8-16 tau).
 
 Every cell's E_c from the graph equals the one-cell API bitwise (same kernels in the same
-order within a cell; lanes only change which cells overlap), and replays of the graph with the
-program's own eager work and synchronisations between them agree with the first one.  Against
-the oracle (cells small enough for it) the FP32 path meets the mixed-path bar of 1e-6 Ha/atom.
-The split-BF16 (3-term) path does not on these strongly coupled small cells (E_c about -14
-Ha/atom, so the bar asks for 7e-8 relative accuracy in E_c; a hi + lo operand keeps 16 bits):
-it is measured at 2.1e-6 and 1.9e-6 Ha/atom on the 3- and 4-atom cells, kept below as a strict
-expected failure,
-and the serving workload runs its mixed path in FP32."""
+order within a cell; lanes only change which cells overlap), replays of the graph with the
+program's own eager work and synchronisations between them agree with the first one, and on
+the cells small enough for the oracle both mixed paths meet the bar of 1e-6 Ha/atom."""
 import sys
 
 import numpy as np
@@ -70,8 +65,7 @@ def test_batch_graph_matches_single_cell_and_oracle(cells, oracle_ec, precision)
         if i in SMALL:
             d = abs(ec[k] - oracle_ec[i]) / inp.natoms
             say("    oracle %.15g, dE/atom %.3g" % (oracle_ec[i], d))
-            if precision == "fp32":
-                assert d <= 1e-6
+            assert d <= 1e-6
     assert np.all(ec < 0)
     for rep in range(3):
         x = torch.randn(1 << 20, device="cuda")
@@ -109,16 +103,3 @@ def test_batch_rejects_bad_cells(cells):
     with pytest.raises(RpaError) as e:
         Batch(ctx, [dict(io, lane=1)], 1)
     assert e.value.code == RPA_ERR_ARG
-
-
-@pytest.mark.xfail(strict=True, reason="3-term split BF16 keeps 16 bits per operand: 2.1e-6 and 1.9e-6 Ha/atom "
-                                       "on the 3- and 4-atom serving cells against the 1e-6 bar (FP32: <= 9e-8)")
-def test_bf16x3_serving_cells_meet_the_energy_bar(cells, oracle_ec):
-    worst = 0.0
-    for i in SMALL:
-        inp = cells[i]
-        d = abs(gpu_pipeline(inp, "bf16x3")["ec"] - oracle_ec[i]) / inp.natoms
-        say("  bf16x3 serving cell %d: dE/atom %.3g" % (i, d))
-        worst = max(worst, d)
-    assert worst <= 1e-6
-
