@@ -155,11 +155,11 @@ def _rho_one_q(inp, vq, iq, omega, A, tol):
     L = np.linalg.cholesky(vq[iq])
     n = inp.nauxtot
     M = LinearOperator((n, n), matvec=lambda x: -(L.conj().T @ op(L @ x)), dtype=np.complex128)
-    return float(eigsh(M, k=1, which="LA", tol=tol, ncv=min(n - 1, 32), v0=np.ones(n, dtype=np.complex128),
+    return float(eigsh(M, k=1, which="LA", tol=tol, ncv=min(n - 1, 16), v0=np.ones(n, dtype=np.complex128),
                        return_eigenvectors=False)[0])
 
 
-def spectral_radius_chi_v(inp, vq=None, qs=None, omega=None, tol=1e-6, workers=1):
+def spectral_radius_chi_v(inp, vq=None, qs=None, omega=None, tol=1e-5, workers=1):
     """max over q of rho(chi(q, i omega) v(q)) = the largest |eigenvalue| of the Hermitian
     negative semidefinite L^H chi(q) L, v(q) = L L^H (Lanczos, relative tolerance tol); omega
     defaults to the smallest grid frequency, where chi(i omega) is largest (every term

@@ -140,3 +140,52 @@ def test_two_species_fullsize_sampled_blocks():
     say("  fp64 worst %.3g, fp32 worst %.3g, bf16x3 worst %.3g, bf16x3 vs fp64 whole tensor %.3g"
         % (e64, e32, eb, wb))
     assert e64 <= 1e-11 and e32 <= 1e-5 and eb <= 3e-5 and wb <= 1e-5
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(1200)
+def test_sheet_gamma_fullsize():
+    """75-atom sheet plus triatomic (Gamma, 1924 NAO / 7440 ABF, 24 tau, 12 A cutoff): sampled
+    blocks against the oracle (sheet-sheet near and far, sheet-adsorbate both orders, adsorbate
+    diagonal), both mixed paths against FP64 over the whole tensor, and E_c of the mixed paths
+    within 1e-6 Ha/atom of the FP64 GPU path (this workload's reference)."""
+    import torch
+    from paper_2407_19930_amd import Context, chi0_R_to_q, chi0_tau_to_omega, rpa_correlation_energy, \
+        rpa_ec_workspace_size
+    inp = cfg(3, with_coulomb=True)
+    say("case sheet Gamma full size: natoms %d nb %d naux %d blocks %d" % (inp.natoms, inp.nb, inp.nauxtot,
+                                                                           len(inp.blocks.I)))
+    samples = [(0, 0, 1, 0), (0, 3, 40, 0), (0, 10, 73, 0), (23, 74, 5, 0), (23, 72, 72, 0)]
+    alg = ochi.Alg1(inp)
+    d = device_inputs(inp)
+    ctx = Context(0)
+    N, nw, nq = inp.nauxtot, len(inp.omega), len(inp.kfrac)
+    vq = torch.from_numpy(inp.vq).cuda()
+    ws = torch.empty(rpa_ec_workspace_size(N, nq, nw), dtype=torch.uint8, device="cuda")
+
+    def energy(chi):
+        chi_w = torch.empty((nw, inp.nR, N, N), dtype=torch.float64, device="cuda")
+        chi0_tau_to_omega(ctx, inp.gamma_cos, chi, chi_w)
+        chi_q = torch.empty((nw, nq, N, N), dtype=torch.complex128, device="cuda")
+        chi0_R_to_q(ctx, inp.cell.mesh, inp.kfrac, chi_w, chi_q)
+        del chi_w
+        ec, _ = rpa_correlation_energy(ctx, inp.womega, chi_q, vq, ws)
+        del chi_q
+        return ec
+
+    chi64, _, _ = gpu_chi_tau(inp, "fp64", ctx=ctx, dev_in=d)
+    e64 = _blocks(inp, chi64, samples, alg)
+    ec64 = energy(chi64)
+    say("  fp64 worst block %.3g, E_c/atom %.12g" % (e64, ec64 / inp.natoms))
+    assert e64 <= 1e-11 and ec64 < 0
+    for prec, blk_tol in (("fp32", 1e-5), ("bf16x3", 3e-5)):
+        chi, _, _ = gpu_chi_tau(inp, prec, ctx=ctx, dev_in=d)
+        eb = _blocks(inp, chi, samples, alg)
+        whole = float(((chi - chi64).norm() / chi64.norm()).item())
+        ec = energy(chi)
+        de = abs(ec - ec64) / inp.natoms
+        say("  %s worst block %.3g, whole tensor vs fp64 %.3g, E_c/atom %.12g, dE/atom %.3g"
+            % (prec, eb, whole, ec / inp.natoms, de))
+        del chi
+        torch.cuda.synchronize()
+        assert eb <= blk_tol and whole <= 1e-5 and de <= 1e-6
