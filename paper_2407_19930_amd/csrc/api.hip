@@ -122,8 +122,20 @@ struct rpa_plan {
   NTiles tiles{};
   PairItems items{};
   PackTables pack{};
+  const int *dgsrc = nullptr;
+  // split-BF16 N stage (BF16X3 plans whose hi and lo parts of transposed G and C each fit a
+  // 32-bit buffer view; other BF16X3 plans run the FP32 N stage)
+  bool nbf16 = false;
+  int nbq = 0;                                  // GT columns: sum of nao rounded up to 8
+  std::vector<int> aopad_off, gsrc;             // per atom GT column offset; GT column -> NAO or -1
+  std::vector<long long> ctn_off;               // per block CtN offset (bf16 elements)
+  long long ctn_elems = 0;
+  std::vector<int> ngrp_start;
+  std::vector<int4> ngrp;
+  std::vector<long long> ngrp_off;
+  unsigned gt_bytes = 0, ct_bytes = 0;          // one part (hi or lo)
   // workspace layout (bytes)
-  size_t ws_cp = 0, ws_cb = 0, ws_g = 0, ws_n = 0, ws_sc = 0, ws_total = 0;
+  size_t ws_cp = 0, ws_cb = 0, ws_g = 0, ws_n = 0, ws_sc = 0, ws_gt = 0, ws_ct = 0, ws_total = 0;
 
   PairItems group_items(const PlanGroup &g) const {
     return PairItems{items.U + g.start, items.V + g.start, items.R + g.start, g.count};
@@ -322,9 +334,15 @@ static int build_impl(rpa_plan *p, const double *G_occ, const double *G_un, cons
   T *Nb = (T *)(ws + p->ws_n);
   double *gpart = (double *)(ws + p->ws_sc);
   int *gexp = sizeof(T) == 4 ? (int *)(gpart + 2 * kGscaleBlocks) : nullptr;
+  const bool nbf = bf16 && p->nbf16;
+  uint16_t *GTh = (uint16_t *)(ws + p->ws_gt), *GTl = (uint16_t *)(ws + p->ws_gt + align_up(p->gt_bytes));
+  uint16_t *Cth = (uint16_t *)(ws + p->ws_ct), *Ctl = (uint16_t *)(ws + p->ws_ct + align_up(p->ct_bytes));
   {
     Timed tm(ctx, "pack_c");
-    HIP_TRY(ctx, launch_pack_c<T>(p->pack, C, Cp, p->maxblk, s));
+    if (nbf)
+      HIP_TRY(ctx, launch_pack_ctn(p->pack, C, Cth, Ctl, p->maxblk, s));
+    else
+      HIP_TRY(ctx, launch_pack_c<T>(p->pack, C, Cp, p->maxblk, s));
     if (bf16) HIP_TRY(ctx, launch_pack_cb(p->pack, C, Cb, p->maxblk * 4, s));
   }
   for (int t = 0; t < p->ntau; ++t) {
@@ -332,10 +350,16 @@ static int build_impl(rpa_plan *p, const double *G_occ, const double *G_un, cons
       Timed tm(ctx, "pad_g");
       if (gexp) HIP_TRY(ctx, launch_gscale(G_occ + t * gstride, G_un + t * gstride, gstride, gpart, gexp, s));
       HIP_TRY(ctx, launch_pad_g<T>(G_occ + t * gstride, G_un + t * gstride, p->nR, p->nb, p->nbp, gexp, Gp, s));
+      if (nbf)
+        HIP_TRY(ctx, launch_pad_gt(G_occ + t * gstride, G_un + t * gstride, p->nR, p->nb, p->nbp, p->nbq, p->dgsrc,
+                                   gexp, GTh, GTl, s));
     }
     {
       Timed tm(ctx, "nstage");
-      HIP_TRY(ctx, launch_nstage<T>(p->tb, p->tiles, Gp, Cp, Nb, s));
+      if (nbf)
+        HIP_TRY(ctx, launch_nstage_bf16(p->tb, p->tiles, GTh, GTl, p->gt_bytes, Cth, Ctl, p->ct_bytes, (float *)Nb, s));
+      else
+        HIP_TRY(ctx, launch_nstage<T>(p->tb, p->tiles, Gp, Cp, Nb, s));
     }
     {
       Timed tm(ctx, "fused");
@@ -451,6 +475,7 @@ int rpa_plan_create(rpa_ctx *ctx, const rpa_cell *cell, const rpa_lri_blocks *bl
   p->in_off.resize(nblk);
   p->out_off.resize(nblk);
   p->cb_off.resize(nblk);
+  p->ctn_off.resize(nblk);
   p->blk_a.resize(nblk);
   p->blk_ni.resize(nblk);
   p->blk_nk.resize(nblk);
@@ -481,6 +506,9 @@ int rpa_plan_create(rpa_ctx *ctx, const rpa_cell *cell, const rpa_lri_blocks *bl
     // split-BF16: [k][mu][hi, lo] rows of 2 x 16 hc slots
     p->cb_off[b] = p->cb_elems;
     p->cb_elems += (long long)p->nao[K] * p->naux[I] * 2 * 16 * (p->nao[I] > 16 ? 2 : 1);
+    // split-BF16 N stage: [(i, mu)][k] with k padded to a multiple of 8
+    p->ctn_off[b] = p->ctn_elems;
+    p->ctn_elems += (long long)p->nao[I] * p->naux[I] * ((p->nao[K] + 7) / 8 * 8);
   }
   p->cp_elems = acc;
   p->nbr_start.assign(na + 1, 0);
@@ -518,6 +546,29 @@ int rpa_plan_create(rpa_ctx *ctx, const rpa_cell *cell, const rpa_lri_blocks *bl
       }
     }
     p->rows_start[V + 1] = (int)p->row_info.size();
+  }
+  // split-BF16 N stage: GT columns padded per atom, contraction rows of V in groups of 8
+  p->aopad_off.assign(na, 0);
+  for (int a = 0; a < na; ++a) {
+    p->aopad_off[a] = p->nbq;
+    p->nbq += (p->nao[a] + 7) / 8 * 8;
+  }
+  p->gsrc.assign(p->nbq, -1);
+  for (int a = 0; a < na; ++a)
+    for (int i = 0; i < p->nao[a]; ++i) p->gsrc[p->aopad_off[a] + i] = p->ao_off[a] + i;
+  p->ngrp_start.assign(na + 1, 0);
+  for (int V = 0; V < na; ++V) {
+    for (int e = p->nbr_start[V]; e < p->nbr_start[V + 1]; ++e) {
+      const int b = order[e], L = p->nbr_K[e];
+      const int st = (p->nao[L] + 7) / 8 * 8;
+      int c0, c1, c2;
+      p->bvk.split(p->nbr_R1[e], c0, c1, c2);
+      for (int c = 0; c < st; c += 8) {
+        p->ngrp.push_back(make_int4(p->aopad_off[L] + c, c0 | (c1 << 10) | (c2 << 20), st, 0));
+        p->ngrp_off.push_back(p->ctn_off[b] + c);
+      }
+    }
+    p->ngrp_start[V + 1] = (int)p->ngrp.size();
   }
   // N buffer offsets: block (V, K, dR) holds [k][s][j][nu]
   const int nR = p->nR;
@@ -615,7 +666,10 @@ int rpa_plan_create(rpa_ctx *ctx, const rpa_cell *cell, const rpa_lri_blocks *bl
                s_pa = add(p->blk_a.data(), nblk * 4), s_pni = add(p->blk_ni.data(), nblk * 4),
                s_pnk = add(p->blk_nk.data(), nblk * 4), s_pst = add(p->blk_stride.data(), nblk * 4),
                s_cst = add(p->cp_stride.data(), na * 4), s_nsl = add(p->nslices.data(), na * 4),
-               s_ncb = add(p->nbr_cb.data(), nblk * 8), s_pcb = add(p->cb_off.data(), nblk * 8);
+               s_ncb = add(p->nbr_cb.data(), nblk * 8), s_pcb = add(p->cb_off.data(), nblk * 8),
+               s_pct = add(p->ctn_off.data(), nblk * 8), s_gsrc = add(p->gsrc.data(), p->gsrc.size() * 4),
+               s_ngs = add(p->ngrp_start.data(), (na + 1) * 4), s_ng = add(p->ngrp.data(), p->ngrp.size() * 16),
+               s_ngo = add(p->ngrp_off.data(), p->ngrp_off.size() * 8);
   hipError_t he = hipSetDevice(ctx->device);
   if (he == hipSuccess) he = hipMalloc(&p->dtab, tot);
   if (he != hipSuccess) {
@@ -650,6 +704,11 @@ int rpa_plan_create(rpa_ctx *ctx, const rpa_cell *cell, const rpa_lri_blocks *bl
   tb.cp_stride = I32(s_cst);
   tb.nslices = I32(s_nsl);
   tb.nbr_cb = I64(s_ncb);
+  tb.ngrp_start = I32(s_ngs);
+  tb.ngrp = (const int4 *)(d + secs[s_ng].off);
+  tb.ngrp_off = I64(s_ngo);
+  tb.nbq = p->nbq;
+  p->dgsrc = I32(s_gsrc);
   tb.natoms = na;
   tb.nb = p->nb;
   tb.nbp = p->nbp;
@@ -658,18 +717,27 @@ int rpa_plan_create(rpa_ctx *ctx, const rpa_cell *cell, const rpa_lri_blocks *bl
   tb.bvk = p->bvk;
   p->tiles = NTiles{I32(s_tV), I32(s_tM), I32(s_tN), (int)p->tileV.size()};
   p->items = PairItems{I32(s_iU), I32(s_iV), I32(s_iR), (int)p->itemU.size()};
-  p->pack = PackTables{I64(s_pin), I64(s_pout), I64(s_pcb), I32(s_pa), I32(s_pni), I32(s_pnk), I32(s_pst), nblk};
+  p->pack = PackTables{I64(s_pin), I64(s_pout), I64(s_pcb), I64(s_pct), I32(s_pa), I32(s_pni), I32(s_pnk), I32(s_pst),
+                       nblk};
 
-  // workspace: packed C (N stage), split-BF16 C (BF16X3 fused kernel), padded G of one tau,
-  // N buffer for one tau, G scale (partial maxima and the two exponents)
+  // workspace: packed C (FP32 / FP64 N stage), split-BF16 C (BF16X3 fused kernel), padded G of
+  // one tau, N buffer for one tau, G scale (partial maxima and the two exponents), and for the
+  // split-BF16 N stage transposed G of one tau and C, hi and lo parts each
   const size_t es = precision == RPA_FP64 ? 8 : 4;
+  const size_t kViewMax = (size_t)0xffff0000u;
+  const size_t gtb = (size_t)2 * nR * p->nbp * p->nbq * 2, ctb = (size_t)p->ctn_elems * 2;
+  p->nbf16 = precision == RPA_BF16X3 && gtb <= kViewMax && ctb <= kViewMax;
+  p->gt_bytes = p->nbf16 ? (unsigned)gtb : 0u;
+  p->ct_bytes = p->nbf16 ? (unsigned)ctb : 0u;
   p->ws_cp = 0;
-  p->ws_cb = align_up(p->cp_elems * es);
+  p->ws_cb = align_up(p->nbf16 ? 0 : p->cp_elems * es);
   p->ws_g = align_up(p->ws_cb + (precision == RPA_BF16X3 ? (size_t)p->cb_elems * 2 : 0));
   const size_t gbytes = 2 * (size_t)nR * p->nbp * p->nbp * es;
   p->ws_n = align_up(p->ws_g + gbytes);
   p->ws_sc = align_up(p->ws_n + (size_t)p->n_elems * es);
-  p->ws_total = align_up(p->ws_sc + 2 * kGscaleBlocks * sizeof(double) + 2 * sizeof(int));
+  p->ws_gt = align_up(p->ws_sc + 2 * kGscaleBlocks * sizeof(double) + 2 * sizeof(int));
+  p->ws_ct = align_up(p->ws_gt + (p->nbf16 ? 2 * align_up(gtb) : 0));
+  p->ws_total = align_up(p->ws_ct + (p->nbf16 ? 2 * align_up(ctb) : 0));
   *workspace_bytes = p->ws_total;
   *out = p;
   return RPA_OK;

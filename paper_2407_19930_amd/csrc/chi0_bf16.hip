@@ -367,3 +367,250 @@ hipError_t launch_fused_bf16(const Chi0Tables &tb, const PairItems &items, int m
     default: return hipErrorInvalidValue;
   }
 }
+
+// ---------------------------------------------------------------------------
+// Split-BF16 N stage.  Same GEMM as the FP32 N stage,
+//   N[(s, dR, k)][(j, nu)] = sum_r A[(s, dR, k)][r] B[r][(j, nu)],
+//   A[(s,dR,k)][r] = G^s(dR - dL)_{g, k},  B[r][(j, nu)] = C^nu_{j l}(V, L, dL),
+// over contraction rows r = (neighbour L(dL) of V, NAO l of L), with both operands stored so
+// that 8 consecutive rows of one neighbour block are 16 contiguous bytes:
+//   GT[s][Y][k][g'] = G^s(Y)_{g k}, the NAO columns g = (L, l) of each atom padded to a multiple
+//     of 8 (g' = aopad_off[L] + l, zero padding), rows k padded to nbp;
+//   CtN[block][j a_V + nu][l'] = C^nu_{j l'} (l' padded to a multiple of 8 with zeros);
+// each split into a hi and a lo bf16 array.  A K step of 32 takes 4 groups of 8 rows; each lane
+// of an MFMA reads its 8 contraction values with one 16-byte LDS load.  N is written in FP32.
+// ---------------------------------------------------------------------------
+namespace {
+
+// CtN of every LRI block into the hi and lo arrays.
+__global__ __launch_bounds__(256) void pack_ctn_kernel(PackTables pt, const double *__restrict__ C,
+                                                       __bf16 *__restrict__ Cth, __bf16 *__restrict__ Ctl) {
+  const int b = blockIdx.x;
+  const int a = pt.a[b], ni = pt.ni[b], nk = pt.nk[b];
+  const int st = (nk + 7) / 8 * 8;
+  const long long total = (long long)ni * a * st;
+  const double *src = C + pt.in_off[b];
+  const long long o = pt.ctn_off[b];
+  for (long long e = (long long)blockIdx.y * blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.y * blockDim.x) {
+    const int lp = (int)(e % st);
+    const long long n = e / st;
+    const int j = (int)(n / a), nu = (int)(n % a);
+    const float x = lp < nk ? (float)src[((long long)nu * ni + j) * nk + lp] : 0.f;
+    __bf16 hi, lo;
+    split_bf16(x, hi, lo);
+    Cth[o + e] = hi;
+    Ctl[o + e] = lo;
+  }
+}
+
+// GT of one tau from G^occ, G^un (FP64 [nR][nb][nb]) times 2^gexp[s]; gsrc[g'] = g or -1.
+__global__ __launch_bounds__(256) void pad_gt_kernel(const double *__restrict__ Gocc, const double *__restrict__ Gun,
+                                                     int nR, int nb, int nbp, int nbq, const int *__restrict__ gsrc,
+                                                     const int *__restrict__ gexp, __bf16 *__restrict__ GTh,
+                                                     __bf16 *__restrict__ GTl) {
+  const double sc0 = ldexp(1.0, gexp[0]), sc1 = ldexp(1.0, gexp[1]);
+  const size_t total = (size_t)2 * nR * nbp * nbq;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const int gp = (int)(e % nbq);
+    const size_t t = e / nbq;
+    const int k = (int)(t % nbp);
+    const size_t sY = t / nbp;
+    const int Y = (int)(sY % nR), s = (int)(sY / nR);
+    const int g = gsrc[gp];
+    float x = 0.f;
+    if (k < nb && g >= 0) x = (float)((s ? Gun : Gocc)[((size_t)Y * nb + g) * nb + k] * (s ? sc1 : sc0));
+    __bf16 hi, lo;
+    split_bf16(x, hi, lo);
+    GTh[e] = hi;
+    GTl[e] = lo;
+  }
+}
+
+constexpr int NB_THREADS = 256;
+constexpr int NB_RS = 40;            // LDS row stride (bf16): 32 contraction values + 8 padding
+
+// gt_bytes, ct_bytes: bytes of one part (hi or lo), at most 2^32 - 2^16 (a masked load sits at
+// the view's end, so offset plus load size never wraps).
+__global__ __launch_bounds__(NB_THREADS) void nstage_bf16_kernel(Chi0Tables tb, NTiles tiles,
+                                                                  const __bf16 *__restrict__ GTh,
+                                                                  const __bf16 *__restrict__ GTl, unsigned gt_bytes,
+                                                                  const __bf16 *__restrict__ Cth,
+                                                                  const __bf16 *__restrict__ Ctl, unsigned ct_bytes,
+                                                                  float *__restrict__ Nbuf) {
+  // [buffer][part hi/lo][128 rows x NB_RS]
+  __shared__ __align__(16) __bf16 As[2][2][128 * NB_RS];
+  __shared__ __align__(16) __bf16 Bs[2][2][128 * NB_RS];
+
+  const int t = blockIdx.x;
+  const int V = tiles.V[t], m0 = tiles.m0[t], n0 = tiles.n0[t];
+  const int nV = tb.nao[V], aV = tb.naux[V];
+  const int NV = nV * aV;
+  const int nbp = tb.nbp, nR = tb.nR, nb = tb.nb, nbq = tb.nbq;
+  const int M = 2 * nR * nbp;
+  const int g0 = tb.ngrp_start[V], ng = tb.ngrp_start[V + 1] - g0;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int col = lane & 15, grp = lane >> 4;
+
+  // loader: row / column tid >> 1 of the tile, groups 2 (tid & 1) and 2 (tid & 1) + 1 of a K step
+  const int lr = tid >> 1, lh = tid & 1;
+  const int m = m0 + lr;
+  const bool mvalid = m < M;
+  int ss = 0, d0 = 0, d1 = 0, d2 = 0, kk = 0;
+  if (mvalid) {
+    ss = m / (nR * nbp);
+    const int rem = m - ss * nR * nbp;
+    const int dR = rem / nbp;
+    kk = rem - dR * nbp;
+    tb.bvk.split(dR, d0, d1, d2);
+  }
+  const int n = n0 + lr;
+  const bool nvalid = n < NV;
+  const __amdgpu_buffer_rsrc_t gvh = buffer_view(GTh, gt_bytes), gvl = buffer_view(GTl, gt_bytes);
+  const __amdgpu_buffer_rsrc_t cvh = buffer_view(Cth, ct_bytes), cvl = buffer_view(Ctl, ct_bytes);
+  const int n0m = tb.bvk.n0, n1m = tb.bvk.n1, n2m = tb.bvk.n2;
+
+  u4 ra[2][2], rb[2][2];                       // [group of the pair][part]
+  auto load = [&](int ks) {
+    // the 4 groups of the K step: wave-uniform table reads (scalar loads)
+    int4 gq[4];
+    long long oq[4];
+    bool vq[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int gi = 4 * ks + q;
+      vq[q] = gi < ng;
+      gq[q] = make_int4(0, 0, 0, 0);
+      oq[q] = 0;
+      if (vq[q]) {
+        gq[q] = tb.ngrp[g0 + gi];              // {A column g', dL packed, CtN row stride, 0}
+        oq[q] = tb.ngrp_off[g0 + gi];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int4 gr = lh ? gq[2 + q] : gq[q];
+      const long long go = lh ? oq[2 + q] : oq[q];
+      const bool valid = lh ? vq[2 + q] : vq[q];
+      unsigned oa = gt_bytes, ob = ct_bytes;  // default: past the view, the load reads zero
+      if (valid && mvalid) {
+        int c0 = d0 - (gr.y & 1023), c1 = d1 - ((gr.y >> 10) & 1023), c2 = d2 - (gr.y >> 20);
+        c0 += c0 < 0 ? n0m : 0;
+        c1 += c1 < 0 ? n1m : 0;
+        c2 += c2 < 0 ? n2m : 0;
+        const int Y = (c0 * n1m + c1) * n2m + c2;
+        oa = (unsigned)(((((size_t)ss * nR + Y) * nbp + kk) * nbq + gr.x) * sizeof(__bf16));
+      }
+      if (valid && nvalid) ob = (unsigned)((go + (size_t)n * gr.z) * sizeof(__bf16));
+      ra[q][0] = __builtin_bit_cast(u4, __builtin_amdgcn_raw_buffer_load_b128(gvh, oa, 0, 0));
+      ra[q][1] = __builtin_bit_cast(u4, __builtin_amdgcn_raw_buffer_load_b128(gvl, oa, 0, 0));
+      rb[q][0] = __builtin_bit_cast(u4, __builtin_amdgcn_raw_buffer_load_b128(cvh, ob, 0, 0));
+      rb[q][1] = __builtin_bit_cast(u4, __builtin_amdgcn_raw_buffer_load_b128(cvl, ob, 0, 0));
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int p = 0; p < 2; ++p) {
+        const int off = lr * NB_RS + 8 * (2 * lh + q);
+        *reinterpret_cast<u4 *>(&As[buf][p][off]) = ra[q][p];
+        *reinterpret_cast<u4 *>(&Bs[buf][p][off]) = rb[q][p];
+      }
+  };
+
+  f4 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = Mfma<float>::zero();
+
+  const int nks = (ng + 3) / 4;
+  load(0);
+  store(0);
+  __syncthreads();
+  for (int ks = 0; ks < nks; ++ks) {
+    const int cur = ks & 1;
+    if (ks + 1 < nks) load(ks + 1);
+    bf8 ah[4], al[4], bh[4], bl[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int oa_ = (wm * 64 + q * 16 + col) * NB_RS + 8 * grp;
+      const int ob_ = (wn * 64 + q * 16 + col) * NB_RS + 8 * grp;
+      ah[q] = *reinterpret_cast<const bf8 *>(&As[cur][0][oa_]);
+      al[q] = *reinterpret_cast<const bf8 *>(&As[cur][1][oa_]);
+      bh[q] = *reinterpret_cast<const bf8 *>(&Bs[cur][0][ob_]);
+      bl[q] = *reinterpret_cast<const bf8 *>(&Bs[cur][1][ob_]);
+    }
+#pragma unroll
+    for (int tm = 0; tm < 4; ++tm)
+#pragma unroll
+      for (int tn = 0; tn < 4; ++tn) acc[tm][tn] = BfMfma<8>::fma(ah[tm], bh[tn], acc[tm][tn]);
+#pragma unroll
+    for (int tm = 0; tm < 4; ++tm)
+#pragma unroll
+      for (int tn = 0; tn < 4; ++tn) acc[tm][tn] = BfMfma<8>::fma(ah[tm], bl[tn], acc[tm][tn]);
+#pragma unroll
+    for (int tm = 0; tm < 4; ++tm)
+#pragma unroll
+      for (int tn = 0; tn < 4; ++tn) acc[tm][tn] = BfMfma<8>::fma(al[tm], bh[tn], acc[tm][tn]);
+    if (ks + 1 < nks) store(cur ^ 1);
+    __syncthreads();
+  }
+
+  // epilogue: scatter rows (s, dR, k) into N blocks (V, K(k), dR), layout [k][s][j][nu]
+#pragma unroll
+  for (int tm = 0; tm < 4; ++tm) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int mm = m0 + wm * 64 + tm * 16 + Mfma<float>::row(grp, r);
+      if (mm >= M) continue;
+      const int s2 = mm / (nR * nbp);
+      const int rem = mm - s2 * nR * nbp;
+      const int dR2 = rem / nbp;
+      const int k2 = rem - dR2 * nbp;
+      if (k2 >= nb) continue;
+      const int K = tb.atom_of_ao[k2];
+      const int kl = k2 - tb.ao_off[K];
+      float *dst = Nbuf + tb.noff[((size_t)V * tb.natoms + K) * nR + dR2] + (size_t)(kl * 2 + s2) * NV;
+#pragma unroll
+      for (int tn = 0; tn < 4; ++tn) {
+        const int nn = n0 + wn * 64 + tn * 16 + col;
+        if (nn < NV) dst[nn] = acc[tm][tn][r];
+      }
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_pack_ctn(const PackTables &pt, const double *C, uint16_t *Cth, uint16_t *Ctl, long long maxblk,
+                           hipStream_t s) {
+  if (pt.nblk == 0) return hipSuccess;
+  const int ychunks = (int)((maxblk + 256 * 16 - 1) / (256 * 16));
+  dim3 grid(pt.nblk, ychunks > 0 ? ychunks : 1);
+  hipLaunchKernelGGL(pack_ctn_kernel, grid, dim3(256), 0, s, pt, C, reinterpret_cast<__bf16 *>(Cth),
+                     reinterpret_cast<__bf16 *>(Ctl));
+  return hipGetLastError();
+}
+
+hipError_t launch_pad_gt(const double *Gocc, const double *Gun, int nR, int nb, int nbp, int nbq, const int *gsrc,
+                         const int *gexp, uint16_t *GTh, uint16_t *GTl, hipStream_t s) {
+  const size_t n = (size_t)2 * nR * nbp * nbq;
+  const int blocks = (int)std::min<size_t>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL(pad_gt_kernel, dim3(blocks), dim3(256), 0, s, Gocc, Gun, nR, nb, nbp, nbq, gsrc, gexp,
+                     reinterpret_cast<__bf16 *>(GTh), reinterpret_cast<__bf16 *>(GTl));
+  return hipGetLastError();
+}
+
+hipError_t launch_nstage_bf16(const Chi0Tables &tb, const NTiles &tiles, const uint16_t *GTh, const uint16_t *GTl,
+                              unsigned gt_bytes, const uint16_t *Cth, const uint16_t *Ctl, unsigned ct_bytes,
+                              float *Nbuf, hipStream_t s) {
+  if (tiles.count == 0) return hipSuccess;
+  hipLaunchKernelGGL(nstage_bf16_kernel, dim3(tiles.count), dim3(NB_THREADS), 0, s, tb, tiles,
+                     reinterpret_cast<const __bf16 *>(GTh), reinterpret_cast<const __bf16 *>(GTl), gt_bytes,
+                     reinterpret_cast<const __bf16 *>(Cth), reinterpret_cast<const __bf16 *>(Ctl), ct_bytes, Nbuf);
+  return hipGetLastError();
+}

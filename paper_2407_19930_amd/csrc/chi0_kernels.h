@@ -14,6 +14,13 @@ struct Chi0Tables {
   const long long *nbr_cp;                    // [nblk] offset of the packed block [k][i][mu]
   const long long *nbr_cb;                    // [nblk] offset of the split-BF16 block (BF16X3 plans)
   const int *nslices;                         // [natoms] sum of nao[K] over the neighbours of U
+  // split-BF16 N stage: groups of 8 contraction rows of atom V (CSR), each {A column g' of the
+  // padded GT layout, BvK components of dL packed as for row_info, CtN row stride, 0} and the
+  // CtN element offset of the group's first row
+  const int *ngrp_start;                      // [natoms + 1]
+  const int4 *ngrp;
+  const long long *ngrp_off;
+  int nbq;                                    // padded NAO columns of GT (sum of nao rounded up to 8)
   // contraction rows of the N-stage for atom V: r in [rows_start[V], rows_start[V+1])
   //   row r <-> (neighbour L(dL) of V, NAO l of L); row_info[r] = {G row ao_off[L] + l,
   //   BvK components of dL packed as d0 | d1 << 10 | d2 << 20, packed-C offset of row
@@ -40,6 +47,7 @@ struct PairItems {   // fused-kernel items: atom pair U <= V and lattice vector 
 struct PackTables {  // repack of the caller's LRI blocks
   const long long *in_off, *out_off;
   const long long *cb_off;                    // split-BF16 layout (BF16X3 plans)
+  const long long *ctn_off;                   // split-BF16 N-stage layout of C (BF16X3 plans)
   const int *a, *ni, *nk, *stride;
   int nblk;
 };
@@ -71,6 +79,15 @@ hipError_t launch_fused(const Chi0Tables &tb, const PairItems &items, int mt, in
 // as uint16_t); ks = O-GEMM steps of 32 for the group's js class.
 int fused_bf16_ks_class(int js_class);
 hipError_t launch_pack_cb(const PackTables &pt, const double *C, uint16_t *Cb, long long maxblk, hipStream_t s);
+// Split-BF16 N stage (see chi0_bf16.hip): C packed once, G transposed and padded per tau,
+// hi / lo parts in separate arrays of below 2^32 bytes each.
+hipError_t launch_pack_ctn(const PackTables &pt, const double *C, uint16_t *Cth, uint16_t *Ctl, long long maxblk,
+                           hipStream_t s);
+hipError_t launch_pad_gt(const double *Gocc, const double *Gun, int nR, int nb, int nbp, int nbq, const int *gsrc,
+                         const int *gexp, uint16_t *GTh, uint16_t *GTl, hipStream_t s);
+hipError_t launch_nstage_bf16(const Chi0Tables &tb, const NTiles &tiles, const uint16_t *GTh, const uint16_t *GTl,
+                              unsigned gt_bytes, const uint16_t *Cth, const uint16_t *Ctl, unsigned ct_bytes,
+                              float *Nbuf, hipStream_t s);
 hipError_t launch_fused_bf16(const Chi0Tables &tb, const PairItems &items, int mt, int ks, int hc, const float *Gp,
                              const uint16_t *Cb, const float *Nbuf, double negs, const int *gexp, double *chi,
                              hipStream_t s);
