@@ -377,7 +377,9 @@ hipError_t launch_fused_bf16(const Chi0Tables &tb, const PairItems &items, int m
 //   GT[s][Y][k][g'] = G^s(Y)_{g k}, the NAO columns g = (L, l) of each atom padded to a multiple
 //     of 8 (g' = aopad_off[L] + l, zero padding), rows k padded to nbp;
 //   CtN[block][j a_V + nu][l'] = C^nu_{j l'} (l' padded to a multiple of 8 with zeros);
-// each split into a hi and a lo bf16 array.  A K step of 32 takes 4 groups of 8 rows; each lane
+// each split into a hi and a lo bf16 array.  GEMM rows run in the order (s, k, dR): the 128
+// rows of a tile then take their A values from G of only two or three NAO rows k (all cells),
+// about 0.1 MB of transposed G per tile, which stays in L2 while the tile gathers it.  A K step of 32 takes 4 groups of 8 rows; each lane
 // of an MFMA reads its 8 contraction values with one 16-byte LDS load.  N is written in FP32.
 // ---------------------------------------------------------------------------
 namespace {
@@ -462,8 +464,8 @@ __global__ __launch_bounds__(NB_THREADS) void nstage_bf16_kernel(Chi0Tables tb, 
   if (mvalid) {
     ss = m / (nR * nbp);
     const int rem = m - ss * nR * nbp;
-    const int dR = rem / nbp;
-    kk = rem - dR * nbp;
+    kk = rem / nR;
+    const int dR = rem - kk * nR;
     tb.bvk.split(dR, d0, d1, d2);
   }
   const int n = n0 + lr;
@@ -560,7 +562,7 @@ __global__ __launch_bounds__(NB_THREADS) void nstage_bf16_kernel(Chi0Tables tb, 
     __syncthreads();
   }
 
-  // epilogue: scatter rows (s, dR, k) into N blocks (V, K(k), dR), layout [k][s][j][nu]
+  // epilogue: scatter rows (s, k, dR) into N blocks (V, K(k), dR), layout [k][s][j][nu]
 #pragma unroll
   for (int tm = 0; tm < 4; ++tm) {
 #pragma unroll
@@ -569,8 +571,8 @@ __global__ __launch_bounds__(NB_THREADS) void nstage_bf16_kernel(Chi0Tables tb, 
       if (mm >= M) continue;
       const int s2 = mm / (nR * nbp);
       const int rem = mm - s2 * nR * nbp;
-      const int dR2 = rem / nbp;
-      const int k2 = rem - dR2 * nbp;
+      const int k2 = rem / nR;
+      const int dR2 = rem - k2 * nR;
       if (k2 >= nb) continue;
       const int K = tb.atom_of_ao[k2];
       const int kl = k2 - tb.ao_off[K];
