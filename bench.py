@@ -53,6 +53,9 @@ def parse():
     ap.add_argument("--ncells", type=int, default=64, help="serving cells used (workload 4; the first n of 64)")
     ap.add_argument("--no-fp64-check", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tuning", default="auto",
+                    help="launch variants of the chi0 kernels: 'auto' (rpa_plan_autotune before the warm-up) or "
+                         "NSTAGE_ORDER,NSTAGE_KSTEP,FUSED_ORDER set explicitly (e.g. 0,16,0, the plan defaults)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a plain 1 GiB device copy first (reference dispatch for the byte counters)")
@@ -68,10 +71,23 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def recorded_traffic(kernel, precision, workload):
+def tuning_tag(tuning):
+    """NSTAGE_ORDER,NSTAGE_KSTEP,FUSED_ORDER of a tuning dict (the form --tuning takes)."""
+    return "%d,%d,%d" % (tuning["nstage_order"], tuning["nstage_kstep"], tuning["fused_order"])
+
+
+def same_variant(kernel, tag_a, tag_b):
+    """Whether two tuning tags launch `kernel` alike: the N stage depends on its order and K
+    step, the fused kernel on its item order only."""
+    a, b = tag_a.split(","), tag_b.split(",")
+    return a[:2] == b[:2] if kernel == "nstage" else a[2] == b[2]
+
+
+def recorded_traffic(kernel, precision, workload, tuning):
     """HBM bytes per launch from the committed counter summary, or None when there is none for
-    this kernel/precision/workload or the kernel sources changed since it was taken.  The
-    summary holds lines `traffic <kernel> <precision> <workload> <bytes per launch> <hash>`."""
+    this kernel/precision/workload and launch variant, or the kernel sources changed since it
+    was taken.  The summary holds lines
+    `traffic <kernel> <precision> <workload> <bytes per launch> <hash> <tuning>`."""
     path = os.path.join(ROOT, "profiles", "pmc_%s_%s_%s.md" % (kernel, workload, precision))
     if not os.path.exists(path):
         return None
@@ -79,7 +95,8 @@ def recorded_traffic(kernel, precision, workload):
     with open(path) as fh:
         for line in fh:
             f = line.strip().strip("`").split()
-            if len(f) == 6 and f[0] == "traffic" and f[1:4] == [kernel, precision, workload]:
+            if len(f) == 7 and f[0] == "traffic" and f[1:4] == [kernel, precision, workload] and \
+                    same_variant(kernel, f[6], tuning_tag(tuning)):
                 return float(f[4]) if f[5] == cur else None
     return None
 
@@ -278,6 +295,13 @@ def main():
         extra["fp64_ms_per_step"] = t64 * 1e3
     plan, ws = make_plan(args.precision)
     alg_flops, exec_flops = plan.flops()
+    if args.tuning == "auto":
+        # times the variants on tau_0 (outside the timed steps); chi_tau[0] is the scratch
+        t = plan.autotune(inp.spin_factor, Gocc, Gun, C, ws, chi_tau[0])
+        log("autotune: %s" % t.as_dict())
+    else:
+        plan.set_tuning(*[int(x) for x in args.tuning.split(",")])
+    tuning = plan.tuning.as_dict()
     for i in range(args.warmup):
         step(plan, ws)
         log("warmup step %d done" % i)
@@ -302,14 +326,15 @@ def main():
     per_launch = st_alg / nt
     avg_ms = kt[dom][0] / max(kt[dom][1], 1)
     achieved = per_launch / (avg_ms * 1e-3) / 1e12
-    # the N stage runs in FP32 on the split-BF16 path; its fused kernel is priced against the
-    # FP32-equivalent split-BF16 peak
+    # split-BF16 kernels are priced against the FP32-equivalent split-BF16 peak; a BF16X3 plan too
+    # large for the split-BF16 N stage runs the FP32 one (it then has a K-step choice)
     if args.precision == "bf16x3":
-        peak = PEAK_BF16X3_FP32EQ if dom == "fused" else PEAK_TFLOPS["fp32"]
+        split_n = tuning["nstage_kstep"] == 0
+        peak = PEAK_BF16X3_FP32EQ if (dom == "fused" or split_n) else PEAK_TFLOPS["fp32"]
     else:
         peak = PEAK_TFLOPS[args.precision]
     roofline = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                "traffic": recorded_traffic(dom, args.precision, cell.name), "kernel": dom,
+                "traffic": recorded_traffic(dom, args.precision, cell.name, tuning), "kernel": dom,
                 "executed_tflops": st_exec / nt / (avg_ms * 1e-3) / 1e12}
 
     if not args.no_fp64_check and args.precision != "fp64":
@@ -341,6 +366,7 @@ def main():
                    "ntau": nt, "rcut": cell.rcut, "lri_blocks": int(len(b.I))},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "tuning": tuning,
         "alg_tflop_per_step": alg_flops / 1e12,
         "exec_tflop_per_step": exec_flops / 1e12,
         "build_ms": build_ms,

@@ -116,6 +116,49 @@ RPA_API int rpa_plan_flops(const rpa_plan *plan, double *alg_flops, double *exec
  * Errors: RPA_ERR_ARG. */
 RPA_API int rpa_plan_stage_flops(const rpa_plan *plan, int stage, double *alg_flops, double *exec_flops);
 
+/* Launch variants of a plan's two chi0 kernels (the tunable part of the batched
+ * build: how the uneven atom-pair work lists are laid over the chip's XCDs, and
+ * the K step of the N-stage GEMM).  Workgroups are dealt to the 8 XCDs (each with
+ * its own L2) round-robin; in the XCD-grouped order each XCD runs one contiguous
+ * range of the plan-order list, so neighbouring tiles or items share its L2.
+ *   nstage_order : 0 plan order, 1 XCD-grouped (N-stage tiles)
+ *   nstage_kstep : 16 or 32 for the FP32 and FP64 N-stage kernel; 0 where the
+ *                  plan's N stage has no such choice (the split-BF16 N stage)
+ *   fused_order  : 0 plan order, 1 XCD-grouped (fused-kernel items)
+ *   from_cache   : 1 if rpa_plan_autotune took the choice from the context's cache
+ *   nstage_ms, fused_ms : measured duration of one tau with the chosen variants
+ *                  (0 when not measured)
+ * Every variant computes the same chi; the item order leaves it bitwise unchanged,
+ * the K step changes the FP32/FP64 summation order only. */
+typedef struct {
+  int nstage_order;
+  int nstage_kstep;
+  int fused_order;
+  int from_cache;
+  double nstage_ms;
+  double fused_ms;
+} rpa_tuning;
+
+/* Autotuner: times every variant of the N-stage kernel, then of the fused kernel,
+ * on the first tau of the given inputs (one warm-up and one timed launch each, HIP
+ * events on the context's stream), keeps the fastest in the plan (the defaults unless
+ * another variant is at least 2% faster) and caches it in
+ * the context under the plan's shape class (precision, atom and basis counts,
+ * lattice-vector count, LRI block count, work-list sizes) and the device's
+ * architecture name; a later plan of the same class takes the cached choice
+ * without timing.  Inputs as for build_chi0_tau; chi0_scratch is a device FP64
+ * buffer of nR * naux_tot^2 elements that receives chi of the first tau.  Blocks
+ * the host until the timing is done.  *out (host, may be null) receives the choice.
+ * Errors: RPA_ERR_ARG, RPA_ERR_WORKSPACE, RPA_ERR_HIP. */
+RPA_API int rpa_plan_autotune(rpa_plan *plan, double spin_factor, const double *G_occ, const double *G_un,
+                              const double *C, void *workspace, size_t workspace_bytes, double *chi0_scratch,
+                              rpa_tuning *out);
+/* The plan's current variants (defaults: plan orders, K step 16).  Errors: RPA_ERR_ARG. */
+RPA_API int rpa_plan_get_tuning(const rpa_plan *plan, rpa_tuning *out);
+/* Sets the variants explicitly (from_cache and the times are ignored); values outside
+ * the ranges above are rejected with RPA_ERR_ARG and leave the plan unchanged. */
+RPA_API int rpa_plan_set_tuning(rpa_plan *plan, const rpa_tuning *t);
+
 /* Opt-in kernel timing with HIP events recorded on the context's stream around
  * every launch of the library's kernels.  rpa_profile(ctx, 1) enables and resets,
  * rpa_profile(ctx, 0) disables.  rpa_profile_read waits for the recorded events and

@@ -24,7 +24,7 @@ EXPORTED = ["rpa_create", "rpa_set_stream", "rpa_destroy", "rpa_last_error", "rp
             "rpa_plan_destroy", "rpa_plan_flops", "rpa_plan_stage_flops", "rpa_profile", "rpa_profile_read",
             "build_chi0_tau", "chi0_tau_to_omega", "chi0_R_to_q", "rpa_ec_workspace_size",
             "rpa_correlation_energy", "rpa_batch_create", "rpa_batch_run", "rpa_batch_result",
-            "rpa_batch_destroy"]
+            "rpa_batch_destroy", "rpa_plan_autotune", "rpa_plan_get_tuning", "rpa_plan_set_tuning"]
 
 
 class RpaError(RuntimeError):
@@ -51,6 +51,15 @@ class _BatchCell(ctypes.Structure):
                 ("build_workspace_bytes", ctypes.c_size_t), ("chi0_tau", ctypes.c_void_p),
                 ("chi0_omega", ctypes.c_void_p), ("chi0_q", ctypes.c_void_p), ("ec_workspace", ctypes.c_void_p),
                 ("ec_workspace_bytes", ctypes.c_size_t)]
+
+
+class Tuning(ctypes.Structure):
+    """rpa_tuning: launch variants of a plan's N-stage and fused kernels."""
+    _fields_ = [("nstage_order", ctypes.c_int), ("nstage_kstep", ctypes.c_int), ("fused_order", ctypes.c_int),
+                ("from_cache", ctypes.c_int), ("nstage_ms", ctypes.c_double), ("fused_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 _lib = None
@@ -89,6 +98,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.rpa_batch_run.argtypes = [vp]
     lib.rpa_batch_result.argtypes = [vp, vp, vp]
     lib.rpa_batch_destroy.argtypes = [vp]
+    lib.rpa_plan_autotune.argtypes = [vp, dp, vp, vp, vp, vp, sz, vp, ctypes.POINTER(Tuning)]
+    lib.rpa_plan_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
+    lib.rpa_plan_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
     for name in EXPORTED:
         if name not in ("rpa_destroy", "rpa_last_error", "rpa_ec_workspace_size"):
             getattr(lib, name).restype = ctypes.c_int
@@ -202,6 +214,30 @@ class Plan:
         a, e = ctypes.c_double(), ctypes.c_double()
         self.ctx.check(self.ctx.lib.rpa_plan_stage_flops(self.h, int(stage), ctypes.byref(a), ctypes.byref(e)))
         return a.value, e.value
+
+    def autotune(self, spin_factor: float, G_occ, G_un, C, workspace, chi0_scratch) -> Tuning:
+        """rpa_plan_autotune on the first tau of the inputs; chi0_scratch: float64 device tensor of
+        nR * naux_tot^2 elements.  Returns the chosen variants."""
+        import torch
+        f64 = torch.float64
+        if chi0_scratch.numel() < self.nR * self.nauxtot ** 2:
+            raise ValueError("chi0_scratch holds fewer than nR * naux_tot^2 elements")
+        t = Tuning()
+        self.ctx.check(self.ctx.lib.rpa_plan_autotune(self.h, float(spin_factor), _dev(G_occ, f64), _dev(G_un, f64),
+                                                      _dev(C, f64), _dev(workspace),
+                                                      workspace.numel() * workspace.element_size(),
+                                                      _dev(chi0_scratch, f64), ctypes.byref(t)))
+        return t
+
+    @property
+    def tuning(self) -> Tuning:
+        t = Tuning()
+        self.ctx.check(self.ctx.lib.rpa_plan_get_tuning(self.h, ctypes.byref(t)))
+        return t
+
+    def set_tuning(self, nstage_order: int, nstage_kstep: int, fused_order: int):
+        t = Tuning(int(nstage_order), int(nstage_kstep), int(fused_order), 0, 0.0, 0.0)
+        self.ctx.check(self.ctx.lib.rpa_plan_set_tuning(self.h, ctypes.byref(t)))
 
     def close(self):
         if getattr(self, "h", None) and getattr(self.ctx, "h", None):

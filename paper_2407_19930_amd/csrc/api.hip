@@ -33,6 +33,8 @@ struct rpa_ctx {
   };
   std::vector<Pending> pending;
   std::map<std::string, std::pair<double, int>> totals;
+  // autotuner choices by plan shape class and device architecture
+  std::map<std::string, rpa_tuning> tune_cache;
 };
 
 namespace {
@@ -69,6 +71,19 @@ struct Timed {
     }
   }
 };
+
+// Order of a work list of n entries in which workgroup b (dealt to XCD b % 8) runs entry
+// perm[b]: XCD x gets the contiguous range [x q + min(x, r), ...) of the plain order, q = n / 8,
+// r = n % 8, so that the entries one XCD runs are neighbours in the plain order.
+std::vector<int> xcd_grouped_order(int n) {
+  std::vector<int> perm(n);
+  const int q = n / 8, r = n % 8;
+  for (int b = 0; b < n; ++b) {
+    const int x = b % 8;
+    perm[b] = x * q + std::min(x, r) + b / 8;
+  }
+  return perm;
+}
 
 int drain_profile(rpa_ctx *ctx) {
   for (auto &p : ctx->pending) {
@@ -123,6 +138,11 @@ struct rpa_plan {
   PairItems items{};
   PackTables pack{};
   const int *dgsrc = nullptr;
+  // XCD-grouped orders of the same tiles and items (items permuted within each group)
+  NTiles tiles_x{};
+  PairItems items_x{};
+  rpa_tuning tune{0, 16, 0, 0, 0.0, 0.0};
+  std::string shape_key;                        // autotuner cache key (without the architecture)
   // split-BF16 N stage (BF16X3 plans whose hi and lo parts of transposed G and C each fit a
   // 32-bit buffer view; other BF16X3 plans run the FP32 N stage)
   bool nbf16 = false;
@@ -137,9 +157,11 @@ struct rpa_plan {
   // workspace layout (bytes)
   size_t ws_cp = 0, ws_cb = 0, ws_g = 0, ws_n = 0, ws_sc = 0, ws_gt = 0, ws_ct = 0, ws_total = 0;
 
-  PairItems group_items(const PlanGroup &g) const {
-    return PairItems{items.U + g.start, items.V + g.start, items.R + g.start, g.count};
+  PairItems group_items(const PlanGroup &g, int order = 0) const {
+    const PairItems &it = order ? items_x : items;
+    return PairItems{it.U + g.start, it.V + g.start, it.R + g.start, g.count};
   }
+  const NTiles &ntiles(int order) const { return order ? tiles_x : tiles; }
 };
 
 // ---- correlation energy ----
@@ -321,60 +343,159 @@ struct rpa_batch {
   hipGraphExec_t exec = nullptr;
 };
 
+// The chi0 build in its steps.  T: precision of G, N and the N stage; bf16: split-BF16 fused
+// kernel and, where the plan allows, split-BF16 N stage (T = float).  G is rescaled per tau
+// by a power of two for the FP32 and BF16X3 paths; the fused kernel's epilogue removes it.
 template <typename T>
-static int build_impl(rpa_plan *p, const double *G_occ, const double *G_un, const double *C, char *ws, double negs,
-                      double *chi0_tau, bool bf16) {
-  rpa_ctx *ctx = p->ctx;
-  hipStream_t s = ctx->stream;
-  const size_t gstride = (size_t)p->nR * p->nb * p->nb;
-  const size_t chistride = (size_t)p->nR * p->nauxtot * p->nauxtot;
-  T *Cp = (T *)(ws + p->ws_cp);
-  uint16_t *Cb = (uint16_t *)(ws + p->ws_cb);
-  T *Gp = (T *)(ws + p->ws_g);
-  T *Nb = (T *)(ws + p->ws_n);
-  double *gpart = (double *)(ws + p->ws_sc);
-  int *gexp = sizeof(T) == 4 ? (int *)(gpart + 2 * kGscaleBlocks) : nullptr;
-  const bool nbf = bf16 && p->nbf16;
-  uint16_t *GTh = (uint16_t *)(ws + p->ws_gt), *GTl = (uint16_t *)(ws + p->ws_gt + align_up(p->gt_bytes));
-  uint16_t *Cth = (uint16_t *)(ws + p->ws_ct), *Ctl = (uint16_t *)(ws + p->ws_ct + align_up(p->ct_bytes));
-  {
+struct BuildSteps {
+  rpa_plan *p;
+  rpa_ctx *ctx;
+  hipStream_t s;
+  char *ws;
+  bool bf16, nbf;
+  size_t gstride, chistride;
+  T *Cp, *Gp, *Nb;
+  uint16_t *Cb, *GTh, *GTl, *Cth, *Ctl;
+  int *gexp;
+  double *gpart;
+
+  BuildSteps(rpa_plan *p_, char *ws_, bool bf16_) : p(p_), ctx(p_->ctx), s(p_->ctx->stream), ws(ws_), bf16(bf16_) {
+    nbf = bf16 && p->nbf16;
+    gstride = (size_t)p->nR * p->nb * p->nb;
+    chistride = (size_t)p->nR * p->nauxtot * p->nauxtot;
+    Cp = (T *)(ws + p->ws_cp);
+    Cb = (uint16_t *)(ws + p->ws_cb);
+    Gp = (T *)(ws + p->ws_g);
+    Nb = (T *)(ws + p->ws_n);
+    gpart = (double *)(ws + p->ws_sc);
+    gexp = sizeof(T) == 4 ? (int *)(gpart + 2 * kGscaleBlocks) : nullptr;
+    GTh = (uint16_t *)(ws + p->ws_gt);
+    GTl = (uint16_t *)(ws + p->ws_gt + align_up(p->gt_bytes));
+    Cth = (uint16_t *)(ws + p->ws_ct);
+    Ctl = (uint16_t *)(ws + p->ws_ct + align_up(p->ct_bytes));
+  }
+  int pack(const double *C) {
     Timed tm(ctx, "pack_c");
     if (nbf)
       HIP_TRY(ctx, launch_pack_ctn(p->pack, C, Cth, Ctl, p->maxblk, s));
     else
       HIP_TRY(ctx, launch_pack_c<T>(p->pack, C, Cp, p->maxblk, s));
     if (bf16) HIP_TRY(ctx, launch_pack_cb(p->pack, C, Cb, p->maxblk * 4, s));
+    return RPA_OK;
   }
-  for (int t = 0; t < p->ntau; ++t) {
-    {
-      Timed tm(ctx, "pad_g");
-      if (gexp) HIP_TRY(ctx, launch_gscale(G_occ + t * gstride, G_un + t * gstride, gstride, gpart, gexp, s));
-      HIP_TRY(ctx, launch_pad_g<T>(G_occ + t * gstride, G_un + t * gstride, p->nR, p->nb, p->nbp, gexp, Gp, s));
-      if (nbf)
-        HIP_TRY(ctx, launch_pad_gt(G_occ + t * gstride, G_un + t * gstride, p->nR, p->nb, p->nbp, p->nbq, p->dgsrc,
-                                   gexp, GTh, GTl, s));
-    }
-    {
-      Timed tm(ctx, "nstage");
-      if (nbf)
-        HIP_TRY(ctx, launch_nstage_bf16(p->tb, p->tiles, GTh, GTl, p->gt_bytes, Cth, Ctl, p->ct_bytes, (float *)Nb, s));
+  int pad(const double *G_occ, const double *G_un, int t) {
+    Timed tm(ctx, "pad_g");
+    if (gexp) HIP_TRY(ctx, launch_gscale(G_occ + t * gstride, G_un + t * gstride, gstride, gpart, gexp, s));
+    HIP_TRY(ctx, launch_pad_g<T>(G_occ + t * gstride, G_un + t * gstride, p->nR, p->nb, p->nbp, gexp, Gp, s));
+    if (nbf)
+      HIP_TRY(ctx, launch_pad_gt(G_occ + t * gstride, G_un + t * gstride, p->nR, p->nb, p->nbp, p->nbq, p->dgsrc,
+                                 gexp, GTh, GTl, s));
+    return RPA_OK;
+  }
+  int nstage(const rpa_tuning &tu) {
+    Timed tm(ctx, "nstage");
+    const NTiles &tiles = p->ntiles(tu.nstage_order);
+    if (nbf)
+      HIP_TRY(ctx, launch_nstage_bf16(p->tb, tiles, GTh, GTl, p->gt_bytes, Cth, Ctl, p->ct_bytes, (float *)Nb, s));
+    else
+      HIP_TRY(ctx, launch_nstage<T>(p->tb, tiles, Gp, Cp, Nb, tu.nstage_kstep, s));
+    return RPA_OK;
+  }
+  int fused(const rpa_tuning &tu, double negs, double *chi_t) {
+    Timed tm(ctx, "fused");
+    for (const PlanGroup &g : p->groups) {
+      if (bf16)
+        HIP_TRY(ctx, launch_fused_bf16(p->tb, p->group_items(g, tu.fused_order), g.mt, fused_bf16_ks_class(g.js), g.hc,
+                                       (const float *)Gp, Cb, (const float *)Nb, negs, gexp, chi_t, s));
       else
-        HIP_TRY(ctx, launch_nstage<T>(p->tb, p->tiles, Gp, Cp, Nb, s));
+        HIP_TRY(ctx, launch_fused<T>(p->tb, p->group_items(g, tu.fused_order), g.mt, g.js, g.hc, Gp, Cp, Nb, negs,
+                                     gexp, chi_t, s));
     }
-    {
-      Timed tm(ctx, "fused");
-      for (const PlanGroup &g : p->groups) {
-        if (bf16)
-          HIP_TRY(ctx, launch_fused_bf16(p->tb, p->group_items(g), g.mt, fused_bf16_ks_class(g.js), g.hc,
-                                         (const float *)Gp, Cb, (const float *)Nb, negs, gexp,
-                                         chi0_tau + t * chistride, s));
-        else
-          HIP_TRY(ctx, launch_fused<T>(p->tb, p->group_items(g), g.mt, g.js, g.hc, Gp, Cp, Nb, negs, gexp,
-                                       chi0_tau + t * chistride, s));
+    return RPA_OK;
+  }
+};
+
+template <typename T>
+static int build_impl(rpa_plan *p, const double *G_occ, const double *G_un, const double *C, char *ws, double negs,
+                      double *chi0_tau, bool bf16) {
+  BuildSteps<T> b(p, ws, bf16);
+  int rc = b.pack(C);
+  for (int t = 0; rc == RPA_OK && t < p->ntau; ++t) {
+    rc = b.pad(G_occ, G_un, t);
+    if (rc == RPA_OK) rc = b.nstage(p->tune);
+    if (rc == RPA_OK) rc = b.fused(p->tune, negs, chi0_tau + t * b.chistride);
+  }
+  return rc;
+}
+
+// Autotuner: each candidate once untimed, once timed between two events on the stream; the plan
+// defaults come first, and a later candidate replaces the best so far only when it is at least
+// kTuneMargin faster (differences within the timing noise keep the default).
+constexpr float kTuneMargin = 0.02f;
+template <typename T>
+static int autotune_impl(rpa_plan *p, const double *G_occ, const double *G_un, const double *C, char *ws, double negs,
+                         double *chi_scratch, bool bf16, rpa_tuning &best) {
+  rpa_ctx *ctx = p->ctx;
+  BuildSteps<T> b(p, ws, bf16);
+  int rc = b.pack(C);
+  if (rc == RPA_OK) rc = b.pad(G_occ, G_un, 0);
+  if (rc != RPA_OK) return rc;
+  hipEvent_t e0, e1;
+  HIP_TRY(ctx, hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    hipEventDestroy(e0);
+    return fail(ctx, RPA_ERR_HIP, "hipEventCreate failed");
+  }
+  auto timed = [&](auto &&step, float &ms) -> int {
+    int r = step();
+    if (r != RPA_OK) return r;
+    if (hipEventRecord(e0, b.s) != hipSuccess) return fail(ctx, RPA_ERR_HIP, "hipEventRecord failed");
+    r = step();
+    if (r != RPA_OK) return r;
+    if (hipEventRecord(e1, b.s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+      return fail(ctx, RPA_ERR_HIP, "timing events failed");
+    return RPA_OK;
+  };
+  best = p->tune;
+  // N stage: tile order x K step (the split-BF16 N stage has no K-step choice)
+  float tbest = 0.f;
+  bool have = false;
+  const int ksteps[2] = {16, 32};
+  const int nk = b.nbf ? 1 : 2;
+  for (int order = 0; rc == RPA_OK && order < 2; ++order)
+    for (int ki = 0; rc == RPA_OK && ki < nk; ++ki) {
+      rpa_tuning c = best;
+      c.nstage_order = order;
+      c.nstage_kstep = b.nbf ? 0 : ksteps[ki];
+      float ms = 0.f;
+      rc = timed([&]() { return b.nstage(c); }, ms);
+      if (rc == RPA_OK && (!have || ms < (1.f - kTuneMargin) * tbest)) {
+        tbest = ms;
+        have = true;
+        best.nstage_order = c.nstage_order;
+        best.nstage_kstep = c.nstage_kstep;
+        best.nstage_ms = ms;
       }
     }
+  // fused kernel on the N of the chosen N stage
+  if (rc == RPA_OK) rc = b.nstage(best);
+  have = false;
+  for (int order = 0; rc == RPA_OK && order < 2; ++order) {
+    rpa_tuning c = best;
+    c.fused_order = order;
+    float ms = 0.f;
+    rc = timed([&]() { return b.fused(c, negs, chi_scratch); }, ms);
+    if (rc == RPA_OK && (!have || ms < (1.f - kTuneMargin) * tbest)) {
+      tbest = ms;
+      have = true;
+      best.fused_order = order;
+      best.fused_ms = ms;
+    }
   }
-  return RPA_OK;
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  return rc;
 }
 
 extern "C" {
@@ -620,6 +741,37 @@ int rpa_plan_create(rpa_ctx *ctx, const rpa_cell *cell, const rpa_lri_blocks *bl
       delete p;
       return fail(ctx, RPA_ERR_UNSUPPORTED, "more than 1024 LRI blocks for one atom");
     }
+  // XCD-grouped copies of the tile list and of each group's items
+  std::vector<int> tileVx, tileMx, tileNx, itemUx, itemVx, itemRx;
+  {
+    const std::vector<int> pt = xcd_grouped_order((int)p->tileV.size());
+    for (int b : pt) {
+      tileVx.push_back(p->tileV[b]);
+      tileMx.push_back(p->tileM[b]);
+      tileNx.push_back(p->tileN[b]);
+    }
+    itemUx.resize(p->itemU.size());
+    itemVx.resize(p->itemU.size());
+    itemRx.resize(p->itemU.size());
+    for (const PlanGroup &g : p->groups) {
+      const std::vector<int> pi = xcd_grouped_order(g.count);
+      for (int b = 0; b < g.count; ++b) {
+        itemUx[g.start + b] = p->itemU[g.start + pi[b]];
+        itemVx[g.start + b] = p->itemV[g.start + pi[b]];
+        itemRx[g.start + b] = p->itemR[g.start + pi[b]];
+      }
+    }
+  }
+  // autotuner shape class: everything the launch shapes and work lists depend on
+  {
+    std::string k = "p" + std::to_string(precision) + " na" + std::to_string(na) + " nb" + std::to_string(p->nb) +
+                    " naux" + std::to_string(p->nauxtot) + " nR" + std::to_string(nR) + " blk" + std::to_string(nblk) +
+                    " tiles" + std::to_string(p->tileV.size());
+    for (const PlanGroup &g : p->groups)
+      k += " g" + std::to_string(g.mt) + "." + std::to_string(g.js) + "." + std::to_string(g.hc) + "." +
+           std::to_string(g.count);
+    p->shape_key = k;
+  }
   // flop model (per tau, times ntau)
   double fN = 0, fX = 0, fMZ = 0, fChi = 0, eN = 0, eFused = 0;
   for (int V = 0; V < na; ++V) fN += 2.0 * nR * 2.0 * p->naux[V] * p->nao[V] * p->nb * (double)S[V];
@@ -670,6 +822,9 @@ int rpa_plan_create(rpa_ctx *ctx, const rpa_cell *cell, const rpa_lri_blocks *bl
                s_pct = add(p->ctn_off.data(), nblk * 8), s_gsrc = add(p->gsrc.data(), p->gsrc.size() * 4),
                s_ngs = add(p->ngrp_start.data(), (na + 1) * 4), s_ng = add(p->ngrp.data(), p->ngrp.size() * 16),
                s_ngo = add(p->ngrp_off.data(), p->ngrp_off.size() * 8);
+  const size_t s_tVx = add(tileVx.data(), tileVx.size() * 4), s_tMx = add(tileMx.data(), tileMx.size() * 4),
+               s_tNx = add(tileNx.data(), tileNx.size() * 4), s_iUx = add(itemUx.data(), itemUx.size() * 4),
+               s_iVx = add(itemVx.data(), itemVx.size() * 4), s_iRx = add(itemRx.data(), itemRx.size() * 4);
   hipError_t he = hipSetDevice(ctx->device);
   if (he == hipSuccess) he = hipMalloc(&p->dtab, tot);
   if (he != hipSuccess) {
@@ -717,6 +872,8 @@ int rpa_plan_create(rpa_ctx *ctx, const rpa_cell *cell, const rpa_lri_blocks *bl
   tb.bvk = p->bvk;
   p->tiles = NTiles{I32(s_tV), I32(s_tM), I32(s_tN), (int)p->tileV.size()};
   p->items = PairItems{I32(s_iU), I32(s_iV), I32(s_iR), (int)p->itemU.size()};
+  p->tiles_x = NTiles{I32(s_tVx), I32(s_tMx), I32(s_tNx), (int)tileVx.size()};
+  p->items_x = PairItems{I32(s_iUx), I32(s_iVx), I32(s_iRx), (int)itemUx.size()};
   p->pack = PackTables{I64(s_pin), I64(s_pout), I64(s_pcb), I64(s_pct), I32(s_pa), I32(s_pni), I32(s_pnk), I32(s_pst),
                        nblk};
 
@@ -729,6 +886,7 @@ int rpa_plan_create(rpa_ctx *ctx, const rpa_cell *cell, const rpa_lri_blocks *bl
   p->nbf16 = precision == RPA_BF16X3 && gtb <= kViewMax && ctb <= kViewMax;
   p->gt_bytes = p->nbf16 ? (unsigned)gtb : 0u;
   p->ct_bytes = p->nbf16 ? (unsigned)ctb : 0u;
+  p->tune.nstage_kstep = p->nbf16 ? 0 : 16;
   p->ws_cp = 0;
   p->ws_cb = align_up(p->nbf16 ? 0 : p->cp_elems * es);
   p->ws_g = align_up(p->ws_cb + (precision == RPA_BF16X3 ? (size_t)p->cb_elems * 2 : 0));
@@ -759,6 +917,60 @@ int rpa_plan_flops(const rpa_plan *p, double *alg, double *exec) {
   if (!p || !alg || !exec) return RPA_ERR_ARG;
   *alg = p->alg_flops;
   *exec = p->exec_flops;
+  return RPA_OK;
+}
+
+static bool tuning_valid(const rpa_plan *p, const rpa_tuning &t) {
+  if (t.nstage_order != 0 && t.nstage_order != 1) return false;
+  if (t.fused_order != 0 && t.fused_order != 1) return false;
+  return p->nbf16 ? t.nstage_kstep == 0 : (t.nstage_kstep == 16 || t.nstage_kstep == 32);
+}
+
+int rpa_plan_get_tuning(const rpa_plan *p, rpa_tuning *out) {
+  if (!p || !out) return RPA_ERR_ARG;
+  *out = p->tune;
+  return RPA_OK;
+}
+
+int rpa_plan_set_tuning(rpa_plan *p, const rpa_tuning *t) {
+  if (!p) return RPA_ERR_ARG;
+  if (!t) return fail(p->ctx, RPA_ERR_ARG, "null tuning");
+  if (!tuning_valid(p, *t))
+    return fail(p->ctx, RPA_ERR_ARG, "tuning out of range (orders 0 or 1; K step 16 or 32, 0 for the split-BF16 N stage)");
+  p->tune = rpa_tuning{t->nstage_order, t->nstage_kstep, t->fused_order, 0, 0.0, 0.0};
+  return RPA_OK;
+}
+
+int rpa_plan_autotune(rpa_plan *p, double spin_factor, const double *G_occ, const double *G_un, const double *C,
+                      void *workspace, size_t workspace_bytes, double *chi0_scratch, rpa_tuning *out) {
+  if (!p) return RPA_ERR_ARG;
+  rpa_ctx *ctx = p->ctx;
+  if (!G_occ || !G_un || !chi0_scratch || !workspace || (p->nblk > 0 && !C))
+    return fail(ctx, RPA_ERR_ARG, "null pointer");
+  if (workspace_bytes < p->ws_total)
+    return fail(ctx, RPA_ERR_WORKSPACE, "workspace smaller than rpa_plan_create reported");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  hipDeviceProp_t prop;
+  HIP_TRY(ctx, hipGetDeviceProperties(&prop, ctx->device));
+  const std::string key = std::string(prop.gcnArchName) + " " + p->shape_key;
+  auto hit = ctx->tune_cache.find(key);
+  if (hit != ctx->tune_cache.end() && tuning_valid(p, hit->second)) {
+    p->tune = hit->second;
+    p->tune.from_cache = 1;
+    p->tune.nstage_ms = p->tune.fused_ms = 0.0;
+  } else {
+    rpa_tuning best{};
+    const double negs = -spin_factor;
+    const int rc = p->prec == RPA_FP64
+                       ? autotune_impl<double>(p, G_occ, G_un, C, (char *)workspace, negs, chi0_scratch, false, best)
+                       : autotune_impl<float>(p, G_occ, G_un, C, (char *)workspace, negs, chi0_scratch,
+                                              p->prec == RPA_BF16X3, best);
+    if (rc != RPA_OK) return rc;
+    best.from_cache = 0;
+    p->tune = best;
+    ctx->tune_cache[key] = best;
+  }
+  if (out) *out = p->tune;
   return RPA_OK;
 }
 

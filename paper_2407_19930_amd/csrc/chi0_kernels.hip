@@ -575,15 +575,15 @@ hipError_t launch_pad_g(const double *Gocc, const double *Gun, int nR, int nb, i
 }
 
 template <typename T>
-hipError_t launch_nstage(const Chi0Tables &tb, const NTiles &tiles, const T *Gp, const T *Cp, T *Nbuf,
+hipError_t launch_nstage(const Chi0Tables &tb, const NTiles &tiles, const T *Gp, const T *Cp, T *Nbuf, int kstep,
                          hipStream_t s) {
   if (tiles.count == 0) return hipSuccess;
-  if (sizeof(T) == 4)
-    // plain FP32 accumulation over the contraction (about 5000 rows on the 8-atom cell): a
-    // second accumulator level (FP32 or FP64) needs 64 or 128 more registers per lane and
-    // halves the occupancy.  K step 16: 37 KB of LDS tiles let four workgroups share a CU
-    // (four waves per SIMD), 13% faster than K step 32 with two despite twice the barriers.
-    hipLaunchKernelGGL((nstage_kernel<T, false, 16, T>), dim3(tiles.count), dim3(NS_THREADS), 0, s, tb, tiles, Gp,
+  // plain accumulation in T over the contraction (about 5000 rows on the 8-atom cell): a
+  // second accumulator level needs 64 or 128 more registers per lane and halves the occupancy.
+  // K step 16 (FP32: 37 KB of LDS tiles, four workgroups per CU) or 32 (twice the LDS, half
+  // the barriers); the plan's tuning picks one, 16 by default.
+  if (kstep == 32)
+    hipLaunchKernelGGL((nstage_kernel<T, false, 32, T>), dim3(tiles.count), dim3(NS_THREADS), 0, s, tb, tiles, Gp,
                        Cp, Nbuf);
   else
     hipLaunchKernelGGL((nstage_kernel<T, false, 16, T>), dim3(tiles.count), dim3(NS_THREADS), 0, s, tb, tiles, Gp,
@@ -658,9 +658,9 @@ template hipError_t launch_pad_g<double>(const double *, const double *, int, in
 template hipError_t launch_pad_g<float>(const double *, const double *, int, int, int, const int *, float *,
                                         hipStream_t);
 template hipError_t launch_nstage<double>(const Chi0Tables &, const NTiles &, const double *, const double *,
-                                          double *, hipStream_t);
+                                          double *, int, hipStream_t);
 template hipError_t launch_nstage<float>(const Chi0Tables &, const NTiles &, const float *, const float *, float *,
-                                         hipStream_t);
+                                         int, hipStream_t);
 template hipError_t launch_fused<double>(const Chi0Tables &, const PairItems &, int, int, int, const double *,
                                          const double *, const double *, double, const int *, double *, hipStream_t);
 template hipError_t launch_fused<float>(const Chi0Tables &, const PairItems &, int, int, int, const float *,

@@ -31,7 +31,7 @@ def test_header_declares_the_four_calls():
     names = header_functions()
     for f in ("build_chi0_tau", "chi0_tau_to_omega", "chi0_R_to_q", "rpa_correlation_energy"):
         assert f in names
-    assert len(names) >= 19
+    assert len(names) >= 22
 
 
 def test_library_exports_every_declared_function(lib):
@@ -82,3 +82,6 @@ def test_host_only_entry_points(lib):
     assert lib.rpa_create(None, 0, None) == 1
     assert lib.build_chi0_tau(None, 2.0, None, None, None, None, 0, None) == 1
     assert lib.rpa_batch_create(None, 1, 1, None, ctypes.byref(out)) == 1
+    assert lib.rpa_plan_get_tuning(None, None) == 1
+    assert lib.rpa_plan_set_tuning(None, None) == 1
+    assert lib.rpa_plan_autotune(None, 2.0, None, None, None, None, 0, None, None) == 1
