@@ -10,6 +10,10 @@
 namespace {
 
 constexpr int ZB = 64, ZK = 16, ZT = 256;
+// LDS tiles are [k][row]; row r of k-row kk sits at r ^ zswz(kk), which puts the 32 lanes of
+// each half wave into distinct bank pairs both for the stores (16 consecutive k of one row, or
+// 32 consecutive rows of one k) and for the MFMA operand reads (16 rows of two k)
+static __device__ __forceinline__ int zswz(int kk) { return ((kk & 1) << 4) | ((kk >> 1) << 1); }
 
 __global__ __launch_bounds__(ZT) void zgemm_kernel(ZgemmArgs g) {
   __shared__ double Ar[2][ZK][ZB], Ai[2][ZK][ZB], Br[2][ZK][ZB], Bi[2][ZK][ZB];
@@ -69,8 +73,8 @@ __global__ __launch_bounds__(ZT) void zgemm_kernel(ZgemmArgs g) {
         row = tid & 63;
         kk = (tid >> 6) + 4 * e;
       }
-      Ar[buf][kk][row] = ra[e].x;
-      Ai[buf][kk][row] = ra[e].y;
+      Ar[buf][kk][row ^ zswz(kk)] = ra[e].x;
+      Ai[buf][kk][row ^ zswz(kk)] = ra[e].y;
       int cc;
       if (g.opB == 0) {
         cc = tid & 63;
@@ -79,8 +83,8 @@ __global__ __launch_bounds__(ZT) void zgemm_kernel(ZgemmArgs g) {
         kk = tid & 15;
         cc = (tid >> 4) + 16 * e;
       }
-      Br[buf][kk][cc] = rb[e].x;
-      Bi[buf][kk][cc] = rb[e].y;
+      Br[buf][kk][cc ^ zswz(kk)] = rb[e].x;
+      Bi[buf][kk][cc ^ zswz(kk)] = rb[e].y;
     }
   };
 
@@ -105,10 +109,10 @@ __global__ __launch_bounds__(ZT) void zgemm_kernel(ZgemmArgs g) {
       double ar[2], ai[2], br[2], bi[2];
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
-        ar[q] = Ar[cur][kk][wm * 32 + q * 16 + col];
-        ai[q] = Ai[cur][kk][wm * 32 + q * 16 + col];
-        br[q] = Br[cur][kk][wn * 32 + q * 16 + col];
-        bi[q] = Bi[cur][kk][wn * 32 + q * 16 + col];
+        ar[q] = Ar[cur][kk][(wm * 32 + q * 16 + col) ^ zswz(kk)];
+        ai[q] = Ai[cur][kk][(wm * 32 + q * 16 + col) ^ zswz(kk)];
+        br[q] = Br[cur][kk][(wn * 32 + q * 16 + col) ^ zswz(kk)];
+        bi[q] = Bi[cur][kk][(wn * 32 + q * 16 + col) ^ zswz(kk)];
       }
 #pragma unroll
       for (int a = 0; a < 2; ++a)
