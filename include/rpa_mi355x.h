@@ -163,7 +163,7 @@ RPA_API int rpa_plan_set_tuning(rpa_plan *plan, const rpa_tuning *t);
  * every launch of the library's kernels.  rpa_profile(ctx, 1) enables and resets,
  * rpa_profile(ctx, 0) disables.  rpa_profile_read waits for the recorded events and
  * returns the summed duration and launch count of one kernel ("pack_c", "pad_g",
- * "nstage", "fused", "cos_transform", "r2q", "ec_stage").  Errors: RPA_ERR_ARG, RPA_ERR_HIP. */
+ * "nstage", "fused", "cos_transform", "r2q", "ec_stage", "green").  Errors: RPA_ERR_ARG, RPA_ERR_HIP. */
 RPA_API int rpa_profile(rpa_ctx *ctx, int enable);
 RPA_API int rpa_profile_read(rpa_ctx *ctx, const char *kernel, double *total_ms, int *launches);
 
@@ -178,6 +178,26 @@ RPA_API int rpa_profile_read(rpa_ctx *ctx, const char *kernel, double *total_ms,
  * Errors: RPA_ERR_ARG, RPA_ERR_WORKSPACE, RPA_ERR_HIP. */
 RPA_API int build_chi0_tau(rpa_plan *plan, double spin_factor, const double *G_occ, const double *G_un,
                    const double *C, void *workspace, size_t workspace_bytes, double *chi0_tau);
+
+/* Green's functions of the chi0 build from Bloch eigenpairs (Sec. 2, Eq. (green_mat), the
+ * factors of i taken out: for tau > 0 the paper's G(R, i tau) = i G^un(R, tau) and
+ * G(R, -i tau) = -i G^occ(R, tau)):
+ *   G^occ_{ij}(R, tau) = (1/N_k) sum_k e^{-i k.R} sum_{n < nocc}  c_{in}(k) c*_{jn}(k) e^{-(mu - eps_nk) tau}
+ *   G^un_{ij}(R, tau)  = (1/N_k) sum_k e^{-i k.R} sum_{n >= nocc} c_{in}(k) c*_{jn}(k) e^{-(eps_nk - mu) tau}
+ * on the BvK lattice vectors of mesh (flattened index n1 N2 N3 + n2 N3 + n3, the order of chi's
+ * R axis), k.R = 2 pi k_frac . n_R.
+ *   tau         : host FP64 [ntau]          k_frac : host FP64 [nk][3]
+ *   eps         : device FP64 [nk][nb], band energies; the first nocc bands are occupied at every k
+ *   wfc         : device complex128 [nk][nb][nb], c_{in}(k) at [k][i][n] (eigenvectors in columns)
+ *   workspace   : device, at least rpa_green_workspace_size(nk, nb, nocc) bytes
+ *   G_occ, G_un : device FP64 [ntau][nR][nb][nb], written in full: the real part (the imaginary
+ *                 part vanishes when H(-k) = H(k)*, as for the real hoppings of the path)
+ * The output is the G_occ / G_un input of build_chi0_tau.  Asynchronous on the context's stream.
+ * Errors: RPA_ERR_ARG, RPA_ERR_UNSUPPORTED (nR * nk > 4096), RPA_ERR_WORKSPACE, RPA_ERR_HIP. */
+RPA_API size_t rpa_green_workspace_size(int nk, int nb, int nocc);
+RPA_API int build_green_tau(rpa_ctx *ctx, int nk, int nb, int nocc, double mu, int ntau, const double *tau,
+                            const int mesh[3], const double *k_frac, const double *eps, const double *wfc,
+                            void *workspace, size_t workspace_bytes, double *G_occ, double *G_un);
 
 /* Cosine transform tau -> i omega (Sec. 2, the chi0(R, i omega_k) equation):
  *   chi(R, i omega_k) = sum_j Gamma_kj chi(R, tau_j),  Gamma_kj = gamma_jk cos(tau_j omega_k)

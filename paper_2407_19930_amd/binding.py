@@ -24,7 +24,8 @@ EXPORTED = ["rpa_create", "rpa_set_stream", "rpa_destroy", "rpa_last_error", "rp
             "rpa_plan_destroy", "rpa_plan_flops", "rpa_plan_stage_flops", "rpa_profile", "rpa_profile_read",
             "build_chi0_tau", "chi0_tau_to_omega", "chi0_R_to_q", "rpa_ec_workspace_size",
             "rpa_correlation_energy", "rpa_batch_create", "rpa_batch_run", "rpa_batch_result",
-            "rpa_batch_destroy", "rpa_plan_autotune", "rpa_plan_get_tuning", "rpa_plan_set_tuning"]
+            "rpa_batch_destroy", "rpa_plan_autotune", "rpa_plan_get_tuning", "rpa_plan_set_tuning",
+            "rpa_green_workspace_size", "build_green_tau"]
 
 
 class RpaError(RuntimeError):
@@ -93,6 +94,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.chi0_R_to_q.argtypes = [vp, ctypes.POINTER(ctypes.c_int), i, sz, i, vp, vp, vp]
     lib.rpa_ec_workspace_size.argtypes = [i, i, i]
     lib.rpa_ec_workspace_size.restype = sz
+    lib.rpa_green_workspace_size.argtypes = [i, i, i]
+    lib.rpa_green_workspace_size.restype = sz
+    lib.build_green_tau.argtypes = [vp, i, i, i, dp, i, vp, ctypes.POINTER(ctypes.c_int), vp, vp, vp, vp, sz, vp, vp]
     lib.rpa_correlation_energy.argtypes = [vp, i, i, i, vp, vp, vp, vp, sz, ctypes.POINTER(dp), vp]
     lib.rpa_batch_create.argtypes = [vp, i, i, ctypes.POINTER(_BatchCell), ctypes.POINTER(vp)]
     lib.rpa_batch_run.argtypes = [vp]
@@ -102,7 +106,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.rpa_plan_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
     lib.rpa_plan_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
     for name in EXPORTED:
-        if name not in ("rpa_destroy", "rpa_last_error", "rpa_ec_workspace_size"):
+        if name not in ("rpa_destroy", "rpa_last_error", "rpa_ec_workspace_size", "rpa_green_workspace_size"):
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -288,6 +292,32 @@ def chi0_R_to_q(ctx: Context, mesh, q_frac, chi0_R, chi0_q):
         raise ValueError("output shape mismatch")
     mesh_a = (ctypes.c_int * 3)(*[int(x) for x in mesh])
     ctx.check(ctx.lib.chi0_R_to_q(ctx.h, mesh_a, nbatch, m, nq, qp, _dev(chi0_R, torch.float64), _dev(out)))
+
+
+def rpa_green_workspace_size(nk: int, nb: int, nocc: int) -> int:
+    return int(load().rpa_green_workspace_size(int(nk), int(nb), int(nocc)))
+
+
+def build_green_tau(ctx: Context, eps, wfc, nocc: int, mu: float, tau, mesh, kfrac, workspace, G_occ, G_un):
+    """G^occ, G^un [ntau, nR, nb, nb] (float64 device) from band energies eps [nk, nb] (float64 device)
+    and eigenvectors wfc [nk, nb, nb] (complex128 device, c_{in}(k) at [k, i, n])."""
+    import torch
+    nk, nb = eps.shape
+    if tuple(wfc.shape) != (nk, nb, nb) or wfc.dtype != torch.complex128:
+        raise ValueError("wfc must be complex128 [nk, nb, nb]")
+    t, tp = _host(tau, np.float64)
+    k, kp = _host(np.asarray(kfrac).reshape(-1, 3), np.float64)
+    if k.shape[0] != nk:
+        raise ValueError("kfrac must have one row per k")
+    nR = int(np.prod(mesh))
+    for G in (G_occ, G_un):
+        if G.numel() != len(t) * nR * nb * nb:
+            raise ValueError("G arrays must hold ntau * nR * nb * nb elements")
+    m = (ctypes.c_int * 3)(*[int(x) for x in mesh])
+    ctx.check(ctx.lib.build_green_tau(ctx.h, nk, nb, int(nocc), float(mu), len(t), tp, m, kp,
+                                      _dev(eps, torch.float64), _dev(wfc, torch.complex128), _dev(workspace),
+                                      workspace.numel() * workspace.element_size(), _dev(G_occ, torch.float64),
+                                      _dev(G_un, torch.float64)))
 
 
 def rpa_ec_workspace_size(n: int, nq: int, nomega: int) -> int:

@@ -9,7 +9,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "librpa_mi355x.so")
-SOURCES = ["api.hip", "chi0_kernels.hip", "chi0_bf16.hip", "transform_kernels.hip", "ec_kernels.hip"]
+SOURCES = ["api.hip", "chi0_kernels.hip", "chi0_bf16.hip", "transform_kernels.hip", "ec_kernels.hip",
+           "green_kernels.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-fvisibility=hidden",
          # no packed FP32 instructions (v_pk_*_f32) anywhere in the device code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
@@ -31,7 +32,7 @@ def build(verbose=False) -> str:
             raise RuntimeError("hipcc failed for %s:\n%s" % (src, r.stderr))
         return obj
 
-    with cf.ThreadPoolExecutor(max_workers=min(5, len(SOURCES))) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(6, len(SOURCES))) as ex:
         objs = list(ex.map(compile_one, SOURCES))
     tmp = OUT + ".tmp"
     cmd = [_hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC"] + objs + ["-o", tmp]

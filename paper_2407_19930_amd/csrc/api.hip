@@ -13,6 +13,7 @@
 #include "../../include/rpa_mi355x.h"
 #include "chi0_kernels.h"
 #include "ec_kernels.h"
+#include "green_kernels.h"
 
 hipError_t launch_cos_transform(const double *W_dev, int ntau, int nomega, size_t n, const double *x, double *y,
                                 hipStream_t s);
@@ -1046,6 +1047,75 @@ int chi0_R_to_q(rpa_ctx *ctx, const int mesh[3], int nbatch, size_t m, int nq, c
   return RPA_OK;
 }
 
+
+// Green's functions: workspace = X (complex [nk][nb][max band count]) + W (complex [nk][nb][nb])
+static void green_layout(int nk, int nb, int nocc, size_t &x_bytes, size_t &total) {
+  const size_t nbs = (size_t)std::max(nocc, nb - nocc);
+  x_bytes = align_up((size_t)nk * nb * nbs * 16);
+  total = x_bytes + align_up((size_t)nk * nb * nb * 16);
+}
+
+size_t rpa_green_workspace_size(int nk, int nb, int nocc) {
+  if (nk <= 0 || nb <= 0 || nocc < 0 || nocc > nb) return 0;
+  size_t x, t;
+  green_layout(nk, nb, nocc, x, t);
+  return t;
+}
+
+int build_green_tau(rpa_ctx *ctx, int nk, int nb, int nocc, double mu, int ntau, const double *tau, const int mesh[3],
+                    const double *k_frac, const double *eps, const double *wfc, void *workspace,
+                    size_t workspace_bytes, double *G_occ, double *G_un) {
+  if (!ctx) return RPA_ERR_ARG;
+  if (!tau || !mesh || !k_frac || !eps || !wfc || !workspace || !G_occ || !G_un)
+    return fail(ctx, RPA_ERR_ARG, "null pointer");
+  if (nk <= 0 || nb <= 0 || ntau <= 0 || nocc < 0 || nocc > nb || mesh[0] <= 0 || mesh[1] <= 0 || mesh[2] <= 0)
+    return fail(ctx, RPA_ERR_ARG, "need nk, nb, ntau, mesh > 0 and 0 <= nocc <= nb");
+  const int nR = mesh[0] * mesh[1] * mesh[2];
+  if ((long long)nR * nk > 4096) return fail(ctx, RPA_ERR_UNSUPPORTED, "nR * nk must not exceed 4096");
+  size_t xb, total;
+  green_layout(nk, nb, nocc, xb, total);
+  if (workspace_bytes < total) return fail(ctx, RPA_ERR_WORKSPACE, "workspace smaller than rpa_green_workspace_size");
+  // phases e^{-i k.R} / N_k, [nR][nk] complex
+  std::vector<double> ph((size_t)2 * nR * nk);
+  for (int r = 0; r < nR; ++r) {
+    const int n3 = r % mesh[2], n2 = (r / mesh[2]) % mesh[1], n1 = r / (mesh[1] * mesh[2]);
+    for (int k = 0; k < nk; ++k) {
+      const double a = -2.0 * M_PI * (k_frac[3 * k] * n1 + k_frac[3 * k + 1] * n2 + k_frac[3 * k + 2] * n3);
+      ph[((size_t)r * nk + k) * 2] = std::cos(a) / nk;
+      ph[((size_t)r * nk + k) * 2 + 1] = std::sin(a) / nk;
+    }
+  }
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  hipStream_t s = ctx->stream;
+  HIP_TRY(ctx, hipMemcpyAsync(ctx->params, ph.data(), ph.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  double *X = (double *)workspace, *W = (double *)((char *)workspace + xb);
+  const size_t m = (size_t)nb * nb, gstride = (size_t)nR * m;
+  Timed tm(ctx, "green");
+  for (int t = 0; t < ntau; ++t)
+    for (int occ = 1; occ >= 0; --occ) {
+      const int n0 = occ ? 0 : nocc, nbs = occ ? nocc : nb - nocc;
+      HIP_TRY(ctx, launch_green_weight(eps, wfc, nk, nb, n0, nbs, mu, tau[t], occ, X, s));
+      // W_k = X_k c_k[:, n0:n0+nbs]^H for every k (an empty band set gives W = 0)
+      ZgemmArgs g{};
+      g.M = g.N = nb;
+      g.K = nbs;
+      g.A = X;
+      g.lda = nbs;
+      g.strideA = (long long)nb * nbs * 2;
+      g.opA = 0;
+      g.B = wfc + 2 * (size_t)n0;
+      g.ldb = nb;
+      g.strideB = (long long)m * 2;
+      g.opB = 1;
+      g.C = W;
+      g.ldc = nb;
+      g.strideC = (long long)m * 2;
+      g.alpha = 1.0;
+      HIP_TRY(ctx, launch_zgemm(g, nk, s));
+      HIP_TRY(ctx, launch_k2r_real(ctx->params, nR, nk, m, W, (occ ? G_occ : G_un) + t * gstride, s));
+    }
+  return RPA_OK;
+}
 
 size_t rpa_ec_workspace_size(int n, int nq, int nomega) {
   if (n <= 0 || nq <= 0 || nomega <= 0) return 0;

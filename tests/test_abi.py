@@ -31,7 +31,7 @@ def test_header_declares_the_four_calls():
     names = header_functions()
     for f in ("build_chi0_tau", "chi0_tau_to_omega", "chi0_R_to_q", "rpa_correlation_energy"):
         assert f in names
-    assert len(names) >= 22
+    assert len(names) >= 24
 
 
 def test_library_exports_every_declared_function(lib):
@@ -85,3 +85,10 @@ def test_host_only_entry_points(lib):
     assert lib.rpa_plan_get_tuning(None, None) == 1
     assert lib.rpa_plan_set_tuning(None, None) == 1
     assert lib.rpa_plan_autotune(None, 2.0, None, None, None, None, 0, None, None) == 1
+    # Green's-function workspace: X for the larger band set plus W, both complex per k
+    nk, nb = 8, 26
+    assert lib.rpa_green_workspace_size(nk, nb, 13) >= 2 * nk * nb * nb * 16 * 3 // 4
+    assert lib.rpa_green_workspace_size(nk, nb, 0) >= 2 * nk * nb * nb * 16
+    assert lib.rpa_green_workspace_size(nk, nb, nb + 1) == 0
+    assert lib.rpa_green_workspace_size(0, nb, 1) == 0
+    assert lib.build_green_tau(None, 1, 1, 0, 0.0, 1, None, None, None, None, None, None, 0, None, None) == 1
