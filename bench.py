@@ -48,7 +48,7 @@ def parse():
     ap.add_argument("--workload", type=int, default=1,
                     help="workload index (1: 8-atom diamond-like cell, 2: 32-atom two-species cell, "
                          "4: 64 serving cells in one graph)")
-    ap.add_argument("--lanes", type=int, default=4, help="concurrent lanes of the serving batch (workload 4)")
+    ap.add_argument("--lanes", type=int, default=8, help="concurrent lanes of the serving batch (workload 4)")
     ap.add_argument("--gen-workers", type=int, default=16, help="processes generating the serving cells")
     ap.add_argument("--ncells", type=int, default=64, help="serving cells used (workload 4; the first n of 64)")
     ap.add_argument("--no-fp64-check", action="store_true")
