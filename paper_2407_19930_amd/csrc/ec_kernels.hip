@@ -15,7 +15,12 @@ constexpr int ZB = 64, ZK = 16, ZT = 256;
 // 32 consecutive rows of one k) and for the MFMA operand reads (16 rows of two k)
 static __device__ __forceinline__ int zswz(int kk) { return ((kk & 1) << 4) | ((kk >> 1) << 1); }
 
-__global__ __launch_bounds__(ZT) void zgemm_kernel(ZgemmArgs g) {
+// OPA / OPB: 0 the operand as stored, 1 its conjugate transpose.  All loads of the K loop are
+// raw buffer loads through views of this block's operands (bytesA, bytesB), unconditional:
+// elements outside M, N or K are addressed past the view and read zero, so no load waits for
+// another and the compiler's wait counts keep the next K step's loads in flight.
+template <int OPA, int OPB>
+__global__ __launch_bounds__(ZT) void zgemm_kernel(ZgemmArgs g, unsigned bytesA, unsigned bytesB) {
   __shared__ double Ar[2][ZK][ZB], Ai[2][ZK][ZB], Br[2][ZK][ZB], Bi[2][ZK][ZB];
   const int n0 = blockIdx.x * ZB, m0 = blockIdx.y * ZB, bz = blockIdx.z;
   if (g.lower_only && n0 > m0 + ZB - 1) return;
@@ -33,56 +38,35 @@ __global__ __launch_bounds__(ZT) void zgemm_kernel(ZgemmArgs g) {
   kbeg = (kbeg / ZK) * ZK;
 
   double2 ra[4], rb[4];
-  auto ld = [&](const double *P, size_t idx) -> double2 { return reinterpret_cast<const double2 *>(P)[idx]; };
+  const __amdgpu_buffer_rsrc_t rA = buffer_view(A, bytesA), rB = buffer_view(B, bytesB);
   auto load = [&](int k0) {
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      double2 va = make_double2(0.0, 0.0), vb = make_double2(0.0, 0.0);
-      if (g.opA == 0) {
-        const int kk = tid & 15, row = (tid >> 4) + 16 * e;
-        if (m0 + row < g.M && k0 + kk < g.K) va = ld(A, (size_t)(m0 + row) * g.lda + k0 + kk);
-      } else {
-        const int row = tid & 63, kk = (tid >> 6) + 4 * e;
-        if (m0 + row < g.M && k0 + kk < g.K) {
-          va = ld(A, (size_t)(k0 + kk) * g.lda + m0 + row);
-          va.y = -va.y;
-        }
-      }
-      if (g.opB == 0) {
-        const int cc = tid & 63, kk = (tid >> 6) + 4 * e;
-        if (n0 + cc < g.N && k0 + kk < g.K) vb = ld(B, (size_t)(k0 + kk) * g.ldb + n0 + cc);
-      } else {
-        const int kk = tid & 15, cc = (tid >> 4) + 16 * e;
-        if (n0 + cc < g.N && k0 + kk < g.K) {
-          vb = ld(B, (size_t)(n0 + cc) * g.ldb + k0 + kk);
-          vb.y = -vb.y;
-        }
-      }
-      ra[e] = va;
-      rb[e] = vb;
+      const int akk = OPA == 0 ? (tid & 15) : (tid >> 6) + 4 * e;
+      const int arow = OPA == 0 ? (tid >> 4) + 16 * e : (tid & 63);
+      const unsigned ia = (unsigned)((OPA == 0 ? (size_t)(m0 + arow) * g.lda + k0 + akk
+                                               : (size_t)(k0 + akk) * g.lda + m0 + arow) * 16);
+      const unsigned oa = ((m0 + arow < g.M) & (k0 + akk < g.K)) ? ia : bytesA;
+      ra[e] = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(rA, oa, 0, 0));
+      if (OPA) ra[e].y = -ra[e].y;
+      const int bkk = OPB == 0 ? (tid >> 6) + 4 * e : (tid & 15);
+      const int bcol = OPB == 0 ? (tid & 63) : (tid >> 4) + 16 * e;
+      const unsigned ib = (unsigned)((OPB == 0 ? (size_t)(k0 + bkk) * g.ldb + n0 + bcol
+                                               : (size_t)(n0 + bcol) * g.ldb + k0 + bkk) * 16);
+      const unsigned ob = ((n0 + bcol < g.N) & (k0 + bkk < g.K)) ? ib : bytesB;
+      rb[e] = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(rB, ob, 0, 0));
+      if (OPB) rb[e].y = -rb[e].y;
     }
   };
   auto store = [&](int buf) {
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      int row, kk;
-      if (g.opA == 0) {
-        kk = tid & 15;
-        row = (tid >> 4) + 16 * e;
-      } else {
-        row = tid & 63;
-        kk = (tid >> 6) + 4 * e;
-      }
+      int kk = OPA == 0 ? (tid & 15) : (tid >> 6) + 4 * e;
+      const int row = OPA == 0 ? (tid >> 4) + 16 * e : (tid & 63);
       Ar[buf][kk][row ^ zswz(kk)] = ra[e].x;
       Ai[buf][kk][row ^ zswz(kk)] = ra[e].y;
-      int cc;
-      if (g.opB == 0) {
-        cc = tid & 63;
-        kk = (tid >> 6) + 4 * e;
-      } else {
-        kk = tid & 15;
-        cc = (tid >> 4) + 16 * e;
-      }
+      kk = OPB == 0 ? (tid >> 6) + 4 * e : (tid & 15);
+      const int cc = OPB == 0 ? (tid & 63) : (tid >> 4) + 16 * e;
       Br[buf][kk][cc ^ zswz(kk)] = rb[e].x;
       Bi[buf][kk][cc ^ zswz(kk)] = rb[e].y;
     }
@@ -95,7 +79,7 @@ __global__ __launch_bounds__(ZT) void zgemm_kernel(ZgemmArgs g) {
     for (int b = 0; b < 2; ++b) accR[a][b] = accI[a][b] = Mfma<double>::zero();
 
   const int nk = g.K > kbeg ? (g.K - kbeg + ZK - 1) / ZK : 0;
-  if (nk > 0) {
+  if (nk > 0) {                            // block-uniform
     load(kbeg);
     store(0);
   }
@@ -366,8 +350,25 @@ hipError_t launch_copy_words(void *dst, const void *src, size_t nwords, hipStrea
 }
 
 hipError_t launch_zgemm(const ZgemmArgs &g, int batch, hipStream_t s) {
+  if (g.M <= 0 || g.N <= 0 || batch <= 0) return hipSuccess;
+  // bytes of one block's operands as addressed (0 for an empty contraction): A is stored
+  // M x K (opA = 0) or K x M, B is stored K x N (opB = 0) or N x K, rows ld elements apart
+  const auto span = [&](int outer, int inner, long long ld) -> size_t {
+    return g.K <= 0 ? 0 : ((size_t)(outer - 1) * ld + inner) * 16;
+  };
+  const size_t ba = g.opA == 0 ? span(g.M, g.K, g.lda) : span(g.K, g.M, g.lda);
+  const size_t bb = g.opB == 0 ? span(g.K, g.N, g.ldb) : span(g.N, g.K, g.ldb);
+  if (ba > 0xffff0000u || bb > 0xffff0000u) return hipErrorInvalidValue;   // 32-bit buffer views
   dim3 grid((g.N + ZB - 1) / ZB, (g.M + ZB - 1) / ZB, batch);
-  hipLaunchKernelGGL(zgemm_kernel, grid, dim3(ZT), 0, s, g);
+  const unsigned ua = (unsigned)ba, ub = (unsigned)bb;
+  if (g.opA == 0 && g.opB == 0)
+    hipLaunchKernelGGL((zgemm_kernel<0, 0>), grid, dim3(ZT), 0, s, g, ua, ub);
+  else if (g.opA == 0)
+    hipLaunchKernelGGL((zgemm_kernel<0, 1>), grid, dim3(ZT), 0, s, g, ua, ub);
+  else if (g.opB == 0)
+    hipLaunchKernelGGL((zgemm_kernel<1, 0>), grid, dim3(ZT), 0, s, g, ua, ub);
+  else
+    hipLaunchKernelGGL((zgemm_kernel<1, 1>), grid, dim3(ZT), 0, s, g, ua, ub);
   return hipGetLastError();
 }
 
