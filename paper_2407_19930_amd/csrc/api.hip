@@ -399,7 +399,7 @@ struct BuildSteps {
     if (nbf)
       HIP_TRY(ctx, launch_nstage_bf16(p->tb, tiles, GTh, GTl, p->gt_bytes, Cth, Ctl, p->ct_bytes, (float *)Nb, s));
     else
-      HIP_TRY(ctx, launch_nstage<T>(p->tb, tiles, Gp, Cp, Nb, tu.nstage_kstep, s));
+      HIP_TRY(ctx, launch_nstage<T>(p->tb, tiles, Gp, Cp, Nb, (size_t)p->cp_elems, tu.nstage_kstep, s));
     return RPA_OK;
   }
   int fused(const rpa_tuning &tu, double negs, double *chi_t) {

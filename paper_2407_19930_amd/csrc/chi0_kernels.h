@@ -64,8 +64,8 @@ template <typename T>
 hipError_t launch_pad_g(const double *Gocc, const double *Gun, int nR, int nb, int nbp, const int *gexp, T *Gp,
                         hipStream_t s);
 template <typename T>
-hipError_t launch_nstage(const Chi0Tables &tb, const NTiles &tiles, const T *Gp, const T *Cp, T *Nbuf, int kstep,
-                         hipStream_t s);  // kstep 16 or 32
+hipError_t launch_nstage(const Chi0Tables &tb, const NTiles &tiles, const T *Gp, const T *Cp, T *Nbuf,
+                         size_t cp_elems, int kstep, hipStream_t s);  // kstep 16 or 32; cp_elems: size of Cp
 // Fused kernel for a group of items whose atoms share the template classes
 // mt = fused_mt_class(naux_U), js = fused_js_class(nao_V) and hc = i-tiles of U (1 or 2).
 int fused_mt_class(int naux);

@@ -128,9 +128,15 @@ template <typename T> struct alignas(16) Vec16 {
   T v[16 / sizeof(T)];
 };
 
-template <typename T, bool kSplit, int BK, typename A2>
+// kBuf: the K loop reads its row records with scalar loads (the 4 rows of a wave's lanes) and A
+// and B through raw buffer views of Gp and Cp (gp_bytes, cp_bytes below 2^32), unconditionally:
+// rows past the contraction or tiles past M or N address the view's end and read zero, so the
+// compiler keeps the next step's loads in flight across the MFMAs.  Without kBuf the loads are
+// masked by branches, and the compiler then waits for them before the MFMAs.
+template <typename T, bool kSplit, int BK, typename A2, bool kBuf>
 __global__ __launch_bounds__(NS_THREADS) void nstage_kernel(Chi0Tables tb, NTiles tiles, const T *__restrict__ Gp,
-                                                            const T *__restrict__ Cp, T *__restrict__ Nbuf) {
+                                                            const T *__restrict__ Cp, T *__restrict__ Nbuf,
+                                                            unsigned gp_bytes, unsigned cp_bytes) {
   typedef typename Mfma<T>::acc Acc;
   constexpr int PAD = sizeof(T) == 4 ? 16 : 8;
   constexpr int RPT = BK / 16;                 // contraction rows per thread and step
@@ -173,6 +179,38 @@ __global__ __launch_bounds__(NS_THREADS) void nstage_kernel(Chi0Tables tb, NTile
   const T *Bbase = Cp + n;
 
   Vec16<T> ra[RPT][NVEC], rb[RPT][NVEC];
+  const __amdgpu_buffer_rsrc_t gview = buffer_view(Gp, gp_bytes), cview = buffer_view(Cp, cp_bytes);
+  const size_t abase = (size_t)ss * nR * plane + kp;
+  // row records of a K step (one per contraction row of this thread), loaded one step ahead
+  // of the data they address; the index is clamped so that the load is unconditional
+  auto load_ri = [&](int k0, int4 (&dst)[RPT]) {
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int r = k0 + rr + 16 * q;
+      dst[q] = tb.row_info[r0 + max(min(r, S - 1), 0)];
+    }
+  };
+  auto load_buf = [&](int k0, const int4 (&rix)[RPT]) {
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int4 ri = rix[q];
+      const bool rvalid = k0 + rr + 16 * q < S;
+      int c0 = d0 - (ri.y & 1023), c1 = d1 - ((ri.y >> 10) & 1023), c2 = d2 - (ri.y >> 20);
+      c0 += c0 < 0 ? n0m : 0;
+      c1 += c1 < 0 ? n1m : 0;
+      c2 += c2 < 0 ? n2m : 0;
+      const int Rp = (c0 * n1m + c1) * n2m + c2;
+      const unsigned ia = (unsigned)((abase + (size_t)Rp * plane + (size_t)ri.x * nbp) * sizeof(T));
+      const unsigned ib = (unsigned)((((long long)(unsigned)ri.z | ((long long)ri.w << 32)) + n) * sizeof(T));
+      const unsigned oa = (rvalid & mvalid) ? ia : gp_bytes;
+      const unsigned ob = (rvalid & nvalid) ? ib : cp_bytes;
+#pragma unroll
+      for (int v = 0; v < NVEC; ++v) {
+        ra[q][v] = __builtin_bit_cast(Vec16<T>, __builtin_amdgcn_raw_buffer_load_b128(gview, oa + 16 * v, 0, 0));
+        rb[q][v] = __builtin_bit_cast(Vec16<T>, __builtin_amdgcn_raw_buffer_load_b128(cview, ob + 16 * v, 0, 0));
+      }
+    }
+  };
   auto load = [&](int k0) {
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
@@ -225,12 +263,28 @@ __global__ __launch_bounds__(NS_THREADS) void nstage_kernel(Chi0Tables tb, NTile
     }
 
   const int nk = (S + BK - 1) / BK;
-  load(0);
+  int4 ri_next[RPT];
+  if (kBuf) {
+    int4 ri0[RPT];
+    load_ri(0, ri0);
+    load_buf(0, ri0);
+    load_ri(BK, ri_next);
+  } else {
+    load(0);
+  }
   store(0);
   __syncthreads();
   for (int it = 0; it < nk; ++it) {
     const int cur = it & 1;
-    if (it + 1 < nk) load((it + 1) * BK);
+    if (kBuf) {
+      // data of step it + 1 (past the last step it reads zero) and the records of step it + 2
+      load_buf((it + 1) * BK, ri_next);
+      load_ri((it + 2) * BK, ri_next);
+      // keep the prefetch ahead of the MFMAs (the scheduler would sink it below them)
+      __builtin_amdgcn_sched_barrier(0);
+    } else if (it + 1 < nk) {
+      load((it + 1) * BK);
+    }
 #pragma unroll
     for (int ks = 0; ks < BK / 4; ++ks) {
       T a[4], b[4];
@@ -254,7 +308,9 @@ __global__ __launch_bounds__(NS_THREADS) void nstage_kernel(Chi0Tables tb, NTile
           acc[a][b] = Mfma<T>::zero();
         }
     }
-    if (it + 1 < nk) store(cur ^ 1);
+    // kBuf: unconditional (past the last step it stores the zeros it loaded into a buffer that
+    // is not read again), so that the compiler cannot sink the prefetch into a branch
+    if (kBuf || it + 1 < nk) store(cur ^ 1);
     __syncthreads();
   }
 
@@ -574,20 +630,31 @@ hipError_t launch_pad_g(const double *Gocc, const double *Gun, int nR, int nb, i
   return hipGetLastError();
 }
 
+template <typename T, int BK>
+static void launch_nstage_bk(const Chi0Tables &tb, const NTiles &tiles, const T *Gp, const T *Cp, T *Nbuf,
+                             size_t gp_bytes, size_t cp_bytes, hipStream_t s) {
+  constexpr size_t kViewMax = 0xffff0000u;
+  if (gp_bytes <= kViewMax && cp_bytes <= kViewMax)
+    hipLaunchKernelGGL((nstage_kernel<T, false, BK, T, true>), dim3(tiles.count), dim3(NS_THREADS), 0, s, tb, tiles,
+                       Gp, Cp, Nbuf, (unsigned)gp_bytes, (unsigned)cp_bytes);
+  else
+    hipLaunchKernelGGL((nstage_kernel<T, false, BK, T, false>), dim3(tiles.count), dim3(NS_THREADS), 0, s, tb, tiles,
+                       Gp, Cp, Nbuf, 0u, 0u);
+}
+
 template <typename T>
-hipError_t launch_nstage(const Chi0Tables &tb, const NTiles &tiles, const T *Gp, const T *Cp, T *Nbuf, int kstep,
-                         hipStream_t s) {
+hipError_t launch_nstage(const Chi0Tables &tb, const NTiles &tiles, const T *Gp, const T *Cp, T *Nbuf,
+                         size_t cp_elems, int kstep, hipStream_t s) {
   if (tiles.count == 0) return hipSuccess;
   // plain accumulation in T over the contraction (about 5000 rows on the 8-atom cell): a
   // second accumulator level needs 64 or 128 more registers per lane and halves the occupancy.
   // K step 16 (FP32: 37 KB of LDS tiles, four workgroups per CU) or 32 (twice the LDS, half
   // the barriers); the plan's tuning picks one, 16 by default.
+  const size_t gp_bytes = (size_t)2 * tb.nR * tb.nbp * tb.nbp * sizeof(T), cp_bytes = cp_elems * sizeof(T);
   if (kstep == 32)
-    hipLaunchKernelGGL((nstage_kernel<T, false, 32, T>), dim3(tiles.count), dim3(NS_THREADS), 0, s, tb, tiles, Gp,
-                       Cp, Nbuf);
+    launch_nstage_bk<T, 32>(tb, tiles, Gp, Cp, Nbuf, gp_bytes, cp_bytes, s);
   else
-    hipLaunchKernelGGL((nstage_kernel<T, false, 16, T>), dim3(tiles.count), dim3(NS_THREADS), 0, s, tb, tiles, Gp,
-                       Cp, Nbuf);
+    launch_nstage_bk<T, 16>(tb, tiles, Gp, Cp, Nbuf, gp_bytes, cp_bytes, s);
   return hipGetLastError();
 }
 
@@ -658,9 +725,9 @@ template hipError_t launch_pad_g<double>(const double *, const double *, int, in
 template hipError_t launch_pad_g<float>(const double *, const double *, int, int, int, const int *, float *,
                                         hipStream_t);
 template hipError_t launch_nstage<double>(const Chi0Tables &, const NTiles &, const double *, const double *,
-                                          double *, int, hipStream_t);
+                                          double *, size_t, int, hipStream_t);
 template hipError_t launch_nstage<float>(const Chi0Tables &, const NTiles &, const float *, const float *, float *,
-                                         int, hipStream_t);
+                                         size_t, int, hipStream_t);
 template hipError_t launch_fused<double>(const Chi0Tables &, const PairItems &, int, int, int, const double *,
                                          const double *, const double *, double, const int *, double *, hipStream_t);
 template hipError_t launch_fused<float>(const Chi0Tables &, const PairItems &, int, int, int, const float *,
