@@ -229,10 +229,10 @@ RPA_API int chi0_R_to_q(rpa_ctx *ctx, const int mesh[3], int nbatch, size_t m, i
  *   womega      : host FP64 [nomega]
  *   chi0_q      : device complex128 [nomega][nq][n][n]
  *   v_q         : device complex128 [nq][n][n], Hermitian positive definite
- *   workspace   : device; rpa_ec_workspace_size(n, nq, nomega) bytes run every
- *                 frequency of a q at once, less (down to the size the same
- *                 formula gives with one frequency per batch) processes the
- *                 frequencies in smaller batches
+ *   workspace   : device; rpa_ec_workspace_size(n, nq, nomega) bytes run the
+ *                 (q, omega) pairs in batches of up to all nq * nomega of them
+ *                 (at most 32 GiB of per-pair matrices); less, down to the size
+ *                 for one pair per batch, runs smaller batches
  *   Ec          : host, E_c per cell (Hartree)
  *   Ec_q        : host [nq] per-q contributions (already divided by nq), or NULL
  * Synchronises the stream.  Errors: RPA_ERR_ARG, RPA_ERR_WORKSPACE,

@@ -199,9 +199,13 @@ EcLayout ec_layout(int n, int nq, int nomega, int cw) {
   return l;
 }
 // default batch: every (q, omega) pair, capped so that T and B stay within 8 GiB
+// (q, omega) pairs per batch for the default workspace: all of them, up to 32 GiB of the two
+// per-pair matrices T and B.  Each batch runs its own sequence of n / 32 Cholesky panel steps,
+// whose diagonal-block kernel costs about the same for one matrix as for many, so fewer and
+// larger batches finish sooner.
 int ec_default_batch(int n, int nq, int nomega) {
   const size_t mat = (size_t)n * n * 16;
-  const size_t cap = std::max<size_t>(1, ((size_t)8 << 30) / (2 * mat));
+  const size_t cap = std::max<size_t>(1, ((size_t)32 << 30) / (2 * mat));
   return (int)std::min<size_t>((size_t)nq * nomega, cap);
 }
 }  // namespace
