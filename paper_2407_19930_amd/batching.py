@@ -9,6 +9,11 @@ import numpy as np
 from .binding import Batch, Plan, rpa_ec_workspace_size
 
 
+# energy-stage workspace per lane: enough for a few hundred (q, omega) matrices of the serving
+# cells at once, while many lanes share one GPU
+EC_LANE_BYTES = 8 << 30
+
+
 def _work(plan: Plan, nq: int, nomega: int) -> float:
     n = plan.nauxtot
     return plan.flops()[0] + 17.0 * nq * nomega * float(n) ** 3
@@ -44,7 +49,8 @@ def make_batch(ctx, cells, nlanes: int, precision: str = "fp32"):
         d["x"] = max(d["x"], max(ntau, 2 * nomega) * nR * n * n)
         d["y"] = max(d["y"], nomega * nR * n * n)
         d["bw"] = max(d["bw"], plans[i].workspace_bytes)
-        d["ew"] = max(d["ew"], rpa_ec_workspace_size(n, nq, nomega))
+        # the energy stage takes the largest (q, omega) batch that fits; lanes keep it modest
+        d["ew"] = max(d["ew"], min(rpa_ec_workspace_size(n, nq, nomega), EC_LANE_BYTES))
     bufs = [dict(x=torch.empty(max(d["x"], 1), dtype=torch.float64, device=dev),
                  y=torch.empty(max(d["y"], 1), dtype=torch.float64, device=dev),
                  bw=torch.empty(d["bw"], dtype=torch.uint8, device=dev),
