@@ -426,6 +426,7 @@ __global__ __launch_bounds__(FU_THREADS) void fused_kernel(Chi0Tables tb, PairIt
       }
       afr[h][st] = v;
     }
+  }
 
   Acc acc[MT];
   double acc64[MT][4];
@@ -453,23 +454,37 @@ __global__ __launch_bounds__(FU_THREADS) void fused_kernel(Chi0Tables tb, PairIt
     const T *NB = Nbuf + tb.noff[((size_t)V * natoms + U) * nR + negR];
     if (wave_active) {
       const int F = 2 * nU * nV;
-      for (int f0 = 0; f0 < F; f0 += 4) {
-        const int f = f0 + grp;
-        const bool fv = f < F;
-        int s = 0, i = 0, j = 0;
-        if (fv) {
-          s = f / (nU * nV);
-          const int rem = f - s * nU * nV;
-          i = rem / nV;
-          j = rem - i * nV;
-        }
-        const T bz = (fv && nu_ok) ? NB[((size_t)(i * 2 + 1 - s) * nV + j) * aV + nu] : T(0);
+      // views of the two N blocks (elements outside them read zero): the loads of ZB iterations
+      // are issued together and waited for once; each accumulator sees the same MFMA sequence
+      const unsigned endA = (unsigned)((size_t)nV * 2 * nU * aU * sizeof(T));
+      const unsigned endB = (unsigned)((size_t)nU * 2 * nV * aV * sizeof(T));
+      const __amdgpu_buffer_rsrc_t vA = buffer_view(NA, endA), vB = buffer_view(NB, endB);
+      constexpr int ZB = sizeof(T) == 4 ? 4 : 2;
+      for (int f0 = 0; f0 < F; f0 += 4 * ZB) {
+        T bz[ZB], az[ZB][MT];
 #pragma unroll
-        for (int m = 0; m < MT; ++m) {
-          const int mu = 16 * m + col;
-          const T az = (fv && mu < aU) ? NA[((size_t)(j * 2 + s) * nU + i) * aU + mu] : T(0);
-          acc[m] = Mfma<T>::fma(az, bz, acc[m]);
+        for (int u = 0; u < ZB; ++u) {
+          const int f = f0 + 4 * u + grp;
+          const bool fv = f < F;
+          const int fc = fv ? f : 0;
+          const int s = fc / (nU * nV);
+          const int rem = fc - s * nU * nV;
+          const int i = rem / nV, j = rem - i * nV;
+          const unsigned ob =
+              (fv && nu_ok) ? (unsigned)((((i * 2 + 1 - s) * nV + j) * aV + nu) * sizeof(T)) : endB;
+          bz[u] = buffer_load<T>(vB, ob);
+#pragma unroll
+          for (int m = 0; m < MT; ++m) {
+            const int mu = 16 * m + col;
+            const unsigned oa =
+                (fv && mu < aU) ? (unsigned)((((j * 2 + s) * nU + i) * aU + mu) * sizeof(T)) : endA;
+            az[u][m] = buffer_load<T>(vA, oa);
+          }
         }
+#pragma unroll
+        for (int u = 0; u < ZB; ++u)
+#pragma unroll
+          for (int m = 0; m < MT; ++m) acc[m] = Mfma<T>::fma(az[u][m], bz[u], acc[m]);
       }
     }
     flush();
