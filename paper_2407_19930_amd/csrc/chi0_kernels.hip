@@ -426,7 +426,6 @@ __global__ __launch_bounds__(FU_THREADS) void fused_kernel(Chi0Tables tb, PairIt
       }
       afr[h][st] = v;
     }
-  }
 
   Acc acc[MT];
   double acc64[MT][4];
