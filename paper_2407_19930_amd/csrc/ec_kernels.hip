@@ -374,38 +374,61 @@ hipError_t launch_zgemm(const ZgemmArgs &g, int batch, hipStream_t s) {
 
 // In-place lower Cholesky of `batch` n x n complex matrices spaced `stride` doubles apart.
 // Wscratch: batch * CB * CB complex; flags[flag_base + m] set non-zero on failure.
+// Right-looking in blocks of np CB-wide panels: the panels of a block are factored in turn
+// (diagonal block, panel solve), each after the block's earlier panels have updated its CB
+// columns, then the trailing matrix takes one rank-(np CB) update.  The trailing update reads
+// and writes the whole remaining matrix, so wider blocks cut that traffic (the diagonal-block
+// kernel stays CB wide: its cost grows with the cube of the width).  Measured: 4 panels for
+// n = 800 and 8 for n = 2400 (energy stage 124 -> 108 ms and 369 -> 304 ms against 1 panel).
+static int chol_panels(int n) { return n >= 1536 ? 8 : 4; }
 hipError_t launch_cholesky(double *A, size_t stride, int n, int batch, double *Wscratch, int *flags, int flag_base,
                            hipStream_t s) {
   hipError_t err = hipSuccess;
-  for (int p = 0; p < n; p += CB) {
-    // one wavefront per diagonal block: its barriers are cheap and the block is small
-    hipLaunchKernelGGL(chol_diag_kernel, dim3(batch), dim3(64), 0, s, A, stride, n, p, Wscratch, flags, flag_base);
-    if ((err = hipGetLastError()) != hipSuccess) return err;
-    const int rest = n - p - CB;
-    if (rest <= 0) break;
-    hipLaunchKernelGGL(chol_trsm_kernel, dim3((rest + 63) / 64, batch), dim3(256), 0, s, A, stride, n, p,
-                       (const double *)Wscratch);
-    if ((err = hipGetLastError()) != hipSuccess) return err;
+  // A[r0.., c0..c0+nc) -= A[r0.., k0..k0+K) A[c0..c0+nc, k0..k0+K)^H for rows r0 <= r < n
+  auto update = [&](int r0, int c0, int nc, int k0, int K, int lower_only) -> hipError_t {
     ZgemmArgs g{};
-    g.M = rest;
-    g.N = rest;
-    g.K = CB;
-    g.A = A + 2 * ((size_t)(p + CB) * n + p);
+    g.M = n - r0;
+    g.N = nc;
+    g.K = K;
+    g.A = A + 2 * ((size_t)r0 * n + k0);
     g.lda = n;
     g.strideA = stride;
     g.opA = 0;
-    g.B = g.A;
+    g.B = A + 2 * ((size_t)c0 * n + k0);
     g.ldb = n;
     g.strideB = stride;
     g.opB = 1;
-    g.C = A + 2 * ((size_t)(p + CB) * n + p + CB);
+    g.C = A + 2 * ((size_t)r0 * n + c0);
     g.ldc = n;
     g.strideC = stride;
     g.alpha = -1.0;
     g.beta = 1.0;
-    g.lower_only = 1;
+    g.lower_only = lower_only;
     g.kmode = 0;
-    if ((err = launch_zgemm(g, batch, s)) != hipSuccess) return err;
+    return launch_zgemm(g, batch, s);
+  };
+  auto panel = [&](int p) -> hipError_t {   // factor columns [p, p + CB) given all updates
+    hipLaunchKernelGGL(chol_diag_kernel, dim3(batch), dim3(64), 0, s, A, stride, n, p, Wscratch, flags, flag_base);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || n - p - CB <= 0) return e;
+    hipLaunchKernelGGL(chol_trsm_kernel, dim3((n - p - CB + 63) / 64, batch), dim3(256), 0, s, A, stride, n, p,
+                       (const double *)Wscratch);
+    return hipGetLastError();
+  };
+  const int np = chol_panels(n);
+  for (int p = 0; p < n; p += np * CB) {
+    for (int j = 0; j < np; ++j) {
+      const int pj = p + j * CB;
+      if (pj >= n) return hipSuccess;
+      // the block's earlier panels' contribution to this panel's columns (rows pj..n; the
+      // diagonal block's upper triangle takes values nothing reads)
+      if (j > 0 && (err = update(pj, pj, std::min(CB, n - pj), p, j * CB, 0)) != hipSuccess) return err;
+      if ((err = panel(pj)) != hipSuccess) return err;
+    }
+    const int t = p + np * CB;
+    if (t >= n) break;
+    // the whole block's contribution to the trailing matrix, lower triangle
+    if ((err = update(t, t, n - t, p, np * CB, 1)) != hipSuccess) return err;
   }
   return hipSuccess;
 }
