@@ -198,7 +198,6 @@ EcLayout ec_layout(int n, int nq, int nomega, int cw) {
   l.cw = cw;
   return l;
 }
-// default batch: every (q, omega) pair, capped so that T and B stay within 8 GiB
 // (q, omega) pairs per batch for the default workspace: all of them, up to 32 GiB of the two
 // per-pair matrices T and B.  Each batch runs its own sequence of n / 32 Cholesky panel steps,
 // whose diagonal-block kernel costs about the same for one matrix as for many, so fewer and

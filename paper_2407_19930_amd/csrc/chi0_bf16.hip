@@ -7,7 +7,8 @@
 // (the dropped a_lo b_lo is below 2^-16 relative), accumulated in FP32 and folded into FP64
 // after every neighbour block.  G is rescaled per tau by a power of two (pad_g), so the
 // split never meets the FP32 subnormal range; the epilogue removes the scale in FP64.
-// The N intermediate stays FP32 (written by the FP32 N stage) and is split in registers.
+// The N intermediate stays FP32 and is split in registers.  It comes from the split-BF16 N stage
+// at the end of this file, or from the FP32 N stage when its operands do not fit 32-bit views.
 #include "chi0_kernels.h"
 
 namespace {
@@ -393,8 +394,9 @@ hipError_t launch_fused_bf16(const Chi0Tables &tb, const PairItems &items, int m
 //   CtN[block][j a_V + nu][l'] = C^nu_{j l'} (l' padded to a multiple of 8 with zeros);
 // each split into a hi and a lo bf16 array.  GEMM rows run in the order (s, k, dR): the 128
 // rows of a tile then take their A values from G of only two or three NAO rows k (all cells),
-// about 0.1 MB of transposed G per tile, which stays in L2 while the tile gathers it.  A K step of 32 takes 4 groups of 8 rows; each lane
-// of an MFMA reads its 8 contraction values with one 16-byte LDS load.  N is written in FP32.
+// about 0.1 MB of transposed G per tile, which stays in L2 while the tile gathers it.  A K step
+// of 32 takes 4 groups of 8 rows; each lane of an MFMA reads its 8 contraction values with one
+// 16-byte LDS load.  N is written in FP32.
 // ---------------------------------------------------------------------------
 namespace {
 
