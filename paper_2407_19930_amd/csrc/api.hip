@@ -641,6 +641,11 @@ int rpa_plan_create(rpa_ctx *ctx, const rpa_cell *cell, const rpa_lri_blocks *bl
   for (int a = 0; a < na; ++a) p->nbr_start[a + 1] += p->nbr_start[a];
   std::vector<int> order(nblk), fill(p->nbr_start.begin(), p->nbr_start.end() - 1);
   for (int b = 0; b < nblk; ++b) order[fill[blocks->I[b]]++] = b;
+  // entries of one neighbourhood grouped by atom K (caller order kept within a group): the
+  // fused kernels walk each group's periodic images together
+  for (int a = 0; a < na; ++a)
+    std::stable_sort(order.begin() + p->nbr_start[a], order.begin() + p->nbr_start[a + 1],
+                     [&](int x, int y) { return blocks->K[x] < blocks->K[y]; });
   p->nbr_K.resize(nblk);
   p->nbr_R1.resize(nblk);
   p->nbr_cp.resize(nblk);

@@ -90,12 +90,12 @@ __global__ __launch_bounds__(FB_THREADS) void fused_bf16_kernel(Chi0Tables tb, P
   constexpr int S = 16 * HC;             // slots per C row and part (hi, lo)
   constexpr int RS = 16 * HC + 4;        // LDS row stride in dwords: hi, lo, 4 dwords of padding
   constexpr int CH = 4 * HC;             // 16-byte chunks per C row
-  constexpr int CG = 4;                  // mu-tiles per group of C fragment reads
+  constexpr int CG = 4;                  // mu-tiles whose C fragments are all read before the O GEMM
   typedef typename BfMfma<KW>::vec CVec;
   typedef typename BfMfma<8>::vec NVec;
   __shared__ __align__(16) unsigned Cs[2][kMaxNaux * RS];
   __shared__ long long nbr_c[kMaxNbr], nbr_n[kMaxNbr];
-  __shared__ int nbr_k[kMaxNbr];
+  __shared__ int nbr_k[kMaxNbr], nbr_g[kMaxNbr];
 
   const int item = blockIdx.x;
   const int U = items.U[item], V = items.V[item], R = items.R[item];
@@ -115,6 +115,9 @@ __global__ __launch_bounds__(FB_THREADS) void fused_bf16_kernel(Chi0Tables tb, P
     nbr_k[e] = tb.nao[K];
     nbr_c[e] = tb.nbr_cb[e0 + e];
     nbr_n[e] = tb.noff[((size_t)V * natoms + K) * nR + tb.bvk.sub(tb.nbr_R1[e0 + e], R)];
+    int f = e + 1;
+    while (f < ne && tb.nbr_K[e0 + f] == K) ++f;
+    nbr_g[e] = f;   // end of the run of entries with the same atom K
   }
 
   // A operand of the O GEMM, split: A[i][j'] = G^un_ij(R) for j' = j < n_V, G^occ_ij(R) for
@@ -204,14 +207,13 @@ __global__ __launch_bounds__(FB_THREADS) void fused_bf16_kernel(Chi0Tables tb, P
   // HC * 512 chunks cover all kMaxNaux rows; rows past aU read zero.
   const unsigned sliceBytes = (unsigned)(aU * CH * 16);
   const size_t sliceElems = (size_t)aU * 2 * S;
-  u4 rc[HC];
-  auto load_slice = [&](const __bf16 *src) {
+  auto load_slice = [&](const __bf16 *src, u4 *rc) {
     const __amdgpu_buffer_rsrc_t r = buffer_view(src, sliceBytes);
 #pragma unroll
     for (int q = 0; q < HC; ++q)
       rc[q] = __builtin_bit_cast(u4, __builtin_amdgcn_raw_buffer_load_b128(r, (unsigned)((tid + q * FB_THREADS) * 16), 0, 0));
   };
-  auto store_slice = [&](int buf) {
+  auto store_slice = [&](int buf, const u4 *rc) {
 #pragma unroll
     for (int q = 0; q < HC; ++q) {
       const int c = tid + q * FB_THREADS;
@@ -221,7 +223,7 @@ __global__ __launch_bounds__(FB_THREADS) void fused_bf16_kernel(Chi0Tables tb, P
   // N rows (FP32): lane (nu, grp) holds j' = 32 ks + 8 grp + e; rows j' >= 2 n_V read zero
   const size_t nstride = (size_t)2 * nV * aV;
   const unsigned nview = wave_active ? (unsigned)(nstride * sizeof(float)) : 0u;
-  float nbA[KS * 8], nbB[KS * 8];
+  float nb0[KS * 8], nb1[KS * 8], nb2[KS * 8];
   auto load_n = [&](const float *nrow, float *dst) {
     const __amdgpu_buffer_rsrc_t r = buffer_view(nrow, nview);
 #pragma unroll
@@ -230,23 +232,61 @@ __global__ __launch_bounds__(FB_THREADS) void fused_bf16_kernel(Chi0Tables tb, P
       for (int e = 0; e < 8; ++e)
         dst[ks * 8 + e] = buffer_load<float>(r, (unsigned)(((32 * ks + 8 * grp + e) * aV + nu) * sizeof(float)));
   };
-  int e = 0, k = 0, cur = 0;
-  // one slice, as in the FP32 kernel: prefetch, O GEMM, chi += C O, stage the next C slice
-  auto slice = [&](const float *nbcur, float *nbnext, bool live) __attribute__((always_inline)) {
-    int e2 = e, k2 = k;
-    if (live) {
+  // Slice order: the entries e of U's neighbourhood come in runs [g0, g1) of one atom K (its
+  // periodic images R1); a run is walked NAO k outer, image inner, so that the workgroups of
+  // one atom pair at different R read the N rows N(V, K, .)[k] of a few hundred KB at about the
+  // same time and share them in L2.  FP32 partial sums are folded into FP64 after every pass
+  // over the images.  The cursor (e, k) runs two slices ahead of the slice being computed.
+  int e = 0, k = 0, g0 = 0, g1 = 0;
+  auto advance = [&]() -> bool {   // next slice; true if the cursor left the last image of a pass
+    int e2 = e + 1, k2 = k;
+    bool fold = false;
+    if (e2 == g1) {
+      fold = true;
+      e2 = g0;
       k2 = k + 1;
-      if (k2 == uniform(nbr_k[e])) {
-        e2 = e + 1;
+      if (k2 == uniform(nbr_k[g0])) {
         k2 = 0;
+        e2 = g1;
+        g0 = g1;
+        g1 = e2 < ne ? uniform(nbr_g[e2]) : g1;
       }
     }
-    const bool more = e2 < ne;
-    const int ea = more ? e2 : 0, ka = more ? k2 : 0;
-    load_slice(Cb + uniform(nbr_c[ea]) + (size_t)ka * sliceElems);
-    load_n(Nbuf + uniform(nbr_n[ea]) + (size_t)ka * nstride, nbnext);
+    e = e2;
+    k = k2;
+    return fold;
+  };
+  // N rows at the cursor into nb, and the cursor's C slice address into cnext (slice 0 again
+  // once the cursor is past the end: in bounds, never used).
+  const __bf16 *cnext = Cb;
+  auto load_at = [&](float *nb) {
+    const bool more = e < ne;
+    const int ea = more ? e : 0, ka = more ? k : 0;
+    cnext = Cb + uniform(nbr_c[ea]) + (size_t)ka * sliceElems;
+    load_n(Nbuf + uniform(nbr_n[ea]) + (size_t)ka * nstride, nb);
+  };
+  bool fcur = false;   // fold after the slice being computed
+  u4 rc[HC];
+  // slice t: loads of slice t + 1's C (into rc) and of slice t + 2's N rows (into nbld), O GEMM and
+  // chi += C O on the N rows of t (nbcur) and the C slice of t in LDS buffer cur, then rc to LDS.
+  // live: t is a slice; live1: t + 1 is a slice.
+  auto slice = [&](const float *nbcur, float *nbld, int cur, bool live, bool live1) __attribute__((always_inline)) {
+    load_slice(cnext, rc);
+    const bool f1 = live1 ? advance() : false;
+    load_at(nbld);
     __builtin_amdgcn_sched_barrier(0);
     if (live && wave_active) {
+      // C fragments of the first M0 mu-tiles (all of them up to CG) first: their LDS reads
+      // complete under the O GEMM; the others are read before the chi MFMAs
+      const unsigned *cs = &Cs[cur][col * RS + grp * (KW / 2)];
+      constexpr int M0 = MT <= CG ? MT : CG - 1, M1 = MT - M0 > 0 ? MT - M0 : 1;
+      CVec ch0[M0], cl0[M0];
+#pragma unroll
+      for (int m = 0; m < M0; ++m) {
+        ch0[m] = *reinterpret_cast<const CVec *>(cs + 16 * m * RS);
+        cl0[m] = *reinterpret_cast<const CVec *>(cs + 16 * m * RS + 8 * HC);
+      }
+      __builtin_amdgcn_sched_barrier(0);
       NVec nh[KS], nl[KS];
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks)
@@ -278,40 +318,47 @@ __global__ __launch_bounds__(FB_THREADS) void fused_bf16_kernel(Chi0Tables tb, P
           bh[4 * h + r] = hi;
           bl[4 * h + r] = lo;
         }
-      const unsigned *cs = &Cs[cur][col * RS + grp * (KW / 2)];
+      CVec ch1[M1], cl1[M1];
 #pragma unroll
-      for (int m0 = 0; m0 < MT; m0 += CG) {
-        CVec chi_h[CG], chi_l[CG];
-#pragma unroll
-        for (int m = m0; m < m0 + CG && m < MT; ++m) {
-          chi_h[m - m0] = *reinterpret_cast<const CVec *>(cs + 16 * m * RS);
-          chi_l[m - m0] = *reinterpret_cast<const CVec *>(cs + 16 * m * RS + 8 * HC);
-        }
-#pragma unroll
-        for (int m = m0; m < m0 + CG && m < MT; ++m) acc[m] = BfMfma<KW>::fma(chi_h[m - m0], bh, acc[m]);
-#pragma unroll
-        for (int m = m0; m < m0 + CG && m < MT; ++m) acc[m] = BfMfma<KW>::fma(chi_h[m - m0], bl, acc[m]);
-#pragma unroll
-        for (int m = m0; m < m0 + CG && m < MT; ++m) acc[m] = BfMfma<KW>::fma(chi_l[m - m0], bh, acc[m]);
+      for (int m = M0; m < MT; ++m) {
+        ch1[m - M0] = *reinterpret_cast<const CVec *>(cs + 16 * m * RS);
+        cl1[m - M0] = *reinterpret_cast<const CVec *>(cs + 16 * m * RS + 8 * HC);
       }
+#pragma unroll
+      for (int m = 0; m < M0; ++m) acc[m] = BfMfma<KW>::fma(ch0[m], bh, acc[m]);
+#pragma unroll
+      for (int m = 0; m < M0; ++m) acc[m] = BfMfma<KW>::fma(ch0[m], bl, acc[m]);
+#pragma unroll
+      for (int m = 0; m < M0; ++m) acc[m] = BfMfma<KW>::fma(cl0[m], bh, acc[m]);
+#pragma unroll
+      for (int m = M0; m < MT; ++m) acc[m] = BfMfma<KW>::fma(ch1[m - M0], bh, acc[m]);
+#pragma unroll
+      for (int m = M0; m < MT; ++m) acc[m] = BfMfma<KW>::fma(ch1[m - M0], bl, acc[m]);
+#pragma unroll
+      for (int m = M0; m < MT; ++m) acc[m] = BfMfma<KW>::fma(cl1[m - M0], bh, acc[m]);
     }
-    if (e2 != e) flush();
-    store_slice(cur ^ 1);
+    if (fcur) flush();
+    fcur = f1;
+    store_slice(cur ^ 1, rc);
     __syncthreads();
-    e = e2;
-    k = k2;
-    cur ^= 1;
   };
 
   const int nsl = tb.nslices[U];
   if (ne > 0) {
-    load_slice(Cb + uniform(nbr_c[0]));
-    store_slice(0);
-    load_n(Nbuf + uniform(nbr_n[0]), nbA);
+    g1 = uniform(nbr_g[0]);
+    load_at(nb0);
+    load_slice(cnext, rc);
+    store_slice(0, rc);
+    fcur = advance();
+    load_at(nb1);
     __syncthreads();
-    for (int t = 0; t < nsl; t += 2) {
-      slice(nbA, nbB, true);
-      slice(nbB, nbA, t + 1 < nsl);
+    for (int t = 0; t < nsl; t += 6) {
+      slice(nb0, nb2, 0, true, t + 1 < nsl);
+      slice(nb1, nb0, 1, t + 1 < nsl, t + 2 < nsl);
+      slice(nb2, nb1, 0, t + 2 < nsl, t + 3 < nsl);
+      slice(nb0, nb2, 1, t + 3 < nsl, t + 4 < nsl);
+      slice(nb1, nb0, 0, t + 4 < nsl, t + 5 < nsl);
+      slice(nb2, nb1, 1, t + 5 < nsl, t + 6 < nsl);
     }
   }
 

@@ -386,7 +386,7 @@ __global__ __launch_bounds__(FU_THREADS) void fused_kernel(Chi0Tables tb, PairIt
   // two C slice buffers; the element after them takes the stores of idle threads
   __shared__ __align__(16) T Cs[2 * kMaxNaux * IP + 4];
   __shared__ long long nbr_c[FU_MAXNBR], nbr_n[FU_MAXNBR];
-  __shared__ int nbr_k[FU_MAXNBR];
+  __shared__ int nbr_k[FU_MAXNBR], nbr_g[FU_MAXNBR];
 
   const int item = blockIdx.x;
   const int U = items.U[item], V = items.V[item], R = items.R[item];
@@ -408,6 +408,9 @@ __global__ __launch_bounds__(FU_THREADS) void fused_kernel(Chi0Tables tb, PairIt
     nbr_k[e] = tb.nao[K];
     nbr_c[e] = tb.nbr_cp[e0 + e];
     nbr_n[e] = tb.noff[((size_t)V * natoms + K) * nR + tb.bvk.sub(tb.nbr_R1[e0 + e], R)];
+    int f = e + 1;
+    while (f < ne && tb.nbr_K[e0 + f] == K) ++f;
+    nbr_g[e] = f;   // end of the run of entries with the same atom K
   }
   for (int e = tid; e < 2 * kMaxNaux * IP + 4; e += FU_THREADS) Cs[e] = T(0);
 
@@ -531,7 +534,11 @@ __global__ __launch_bounds__(FU_THREADS) void fused_kernel(Chi0Tables tb, PairIt
 #pragma unroll
     for (int st = 0; st < JS; ++st) dst[st] = buffer_load<T>(r, (unsigned)(((4 * st + grp) * aV + nu) * sizeof(T)));
   };
-  int e = 0, k = 0, cur = 0;
+  // Slice order: the entries e of U's neighbourhood come in runs [g0, g1) of one atom K (its
+  // periodic images R1); a run is walked NAO k outer, image inner, so that the workgroups of
+  // one atom pair at different R read the N rows N(V, K, .)[k] at about the same time and
+  // share them in L2.  Partial sums are folded into FP64 after every pass over the images.
+  int e = 0, k = 0, cur = 0, g0 = 0, g1 = 0;
   // one slice: prefetch C and N of the next slice (slice (0, 0) again after the last),
   // O GEMM, chi += C O, stage the next C slice, barrier.  The loop runs over pairs of slices;
   // the second slice of the last pair may be past the end, and then only its GEMMs are
@@ -539,11 +546,17 @@ __global__ __launch_bounds__(FU_THREADS) void fused_kernel(Chi0Tables tb, PairIt
   // compiler derives are exact and the prefetch stays in flight across the barrier.
   auto slice = [&](const T *nbcur, T *nbnext, bool live) __attribute__((always_inline)) {
     int e2 = e, k2 = k;
+    bool fold = false;
     if (live) {
-      k2 = k + 1;
-      if (k2 == uniform(nbr_k[e])) {
-        e2 = e + 1;
-        k2 = 0;
+      e2 = e + 1;
+      if (e2 == g1) {
+        fold = true;
+        e2 = g0;
+        k2 = k + 1;
+        if (k2 == uniform(nbr_k[g0])) {
+          k2 = 0;
+          e2 = g1;
+        }
       }
     }
     // past the last slice the loads go to slice (0, 0), which every item has (ne > 0)
@@ -579,9 +592,13 @@ __global__ __launch_bounds__(FU_THREADS) void fused_kernel(Chi0Tables tb, PairIt
             for (int m = m0; m < m0 + CG && m < MT; ++m) acc[m] = Mfma<T>::fma(c[m - m0][r], o[h][r], acc[m]);
         }
     }
-    if (e2 != e) flush();
+    if (fold) flush();
     store_slice(cur ^ 1);
     __syncthreads();
+    if (fold && e2 == g1) {
+      g0 = g1;
+      g1 = more ? uniform(nbr_g[ea]) : g1;
+    }
     e = e2;
     k = k2;
     cur ^= 1;
@@ -593,6 +610,7 @@ __global__ __launch_bounds__(FU_THREADS) void fused_kernel(Chi0Tables tb, PairIt
     store_slice(0);
     load_n(Nbuf + uniform(nbr_n[0]), nbA);
     __syncthreads();
+    g1 = uniform(nbr_g[0]);
     for (int t = 0; t < nsl; t += 2) {
       slice(nbA, nbB, true);
       slice(nbB, nbA, t + 1 < nsl);
