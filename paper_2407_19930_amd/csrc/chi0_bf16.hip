@@ -235,22 +235,27 @@ __global__ __launch_bounds__(FB_THREADS) void fused_bf16_kernel(Chi0Tables tb, P
   // Slice order: the entries e of U's neighbourhood come in runs [g0, g1) of one atom K (its
   // periodic images R1); a run is walked NAO k outer, image inner, so that the workgroups of
   // one atom pair at different R read the N rows N(V, K, .)[k] of a few hundred KB at about the
-  // same time and share them in L2.  FP32 partial sums are folded into FP64 after every pass
-  // over the images.  The cursor (e, k) runs two slices ahead of the slice being computed.
-  int e = 0, k = 0, g0 = 0, g1 = 0;
-  auto advance = [&]() -> bool {   // next slice; true if the cursor left the last image of a pass
+  // same time and share them in L2.  FP32 partial sums are folded into FP64 at the end of a pass
+  // over the images once kFoldSlices slices have been added since the last fold, and at the end
+  // of each run.  The cursor (e, k) runs two slices ahead of the slice being computed.
+  int e = 0, k = 0, g0 = 0, g1 = 0, run = 0;
+  auto advance = [&]() -> bool {   // next slice; true if the slice left is followed by a fold
     int e2 = e + 1, k2 = k;
     bool fold = false;
+    ++run;
     if (e2 == g1) {
-      fold = true;
       e2 = g0;
       k2 = k + 1;
+      bool run_end = false;
       if (k2 == uniform(nbr_k[g0])) {
         k2 = 0;
         e2 = g1;
         g0 = g1;
         g1 = e2 < ne ? uniform(nbr_g[e2]) : g1;
+        run_end = true;
       }
+      fold = run_end || run >= kFoldSlices;
+      if (fold) run = 0;
     }
     e = e2;
     k = k2;

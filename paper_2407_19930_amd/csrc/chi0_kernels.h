@@ -96,3 +96,5 @@ hipError_t launch_fused_bf16(const Chi0Tables &tb, const PairItems &items, int m
 constexpr int kMaxNao = 32;     // NAOs per atom
 constexpr int kMaxNaux = 128;   // ABFs per atom
 constexpr int kMaxNbr = 1024;   // LRI blocks (neighbours) per atom
+// fused kernels: FP32 partial sums are folded into FP64 after at least this many K(R1) slices
+constexpr int kFoldSlices = 16;

@@ -537,8 +537,9 @@ __global__ __launch_bounds__(FU_THREADS) void fused_kernel(Chi0Tables tb, PairIt
   // Slice order: the entries e of U's neighbourhood come in runs [g0, g1) of one atom K (its
   // periodic images R1); a run is walked NAO k outer, image inner, so that the workgroups of
   // one atom pair at different R read the N rows N(V, K, .)[k] at about the same time and
-  // share them in L2.  Partial sums are folded into FP64 after every pass over the images.
-  int e = 0, k = 0, cur = 0, g0 = 0, g1 = 0;
+  // share them in L2.  Partial sums are folded into FP64 at the end of a pass over the images
+  // once kFoldSlices slices have been added since the last fold, and at the end of each run.
+  int e = 0, k = 0, cur = 0, g0 = 0, g1 = 0, run = 0;
   // one slice: prefetch C and N of the next slice (slice (0, 0) again after the last),
   // O GEMM, chi += C O, stage the next C slice, barrier.  The loop runs over pairs of slices;
   // the second slice of the last pair may be past the end, and then only its GEMMs are
@@ -546,17 +547,20 @@ __global__ __launch_bounds__(FU_THREADS) void fused_kernel(Chi0Tables tb, PairIt
   // compiler derives are exact and the prefetch stays in flight across the barrier.
   auto slice = [&](const T *nbcur, T *nbnext, bool live) __attribute__((always_inline)) {
     int e2 = e, k2 = k;
-    bool fold = false;
+    bool pass_end = false, fold = false;
     if (live) {
       e2 = e + 1;
+      ++run;
       if (e2 == g1) {
-        fold = true;
+        pass_end = true;
         e2 = g0;
         k2 = k + 1;
         if (k2 == uniform(nbr_k[g0])) {
           k2 = 0;
           e2 = g1;
         }
+        fold = e2 == g1 || run >= kFoldSlices;
+        if (fold) run = 0;
       }
     }
     // past the last slice the loads go to slice (0, 0), which every item has (ne > 0)
@@ -595,7 +599,7 @@ __global__ __launch_bounds__(FU_THREADS) void fused_kernel(Chi0Tables tb, PairIt
     if (fold) flush();
     store_slice(cur ^ 1);
     __syncthreads();
-    if (fold && e2 == g1) {
+    if (pass_end && e2 == g1) {
       g0 = g1;
       g1 = more ? uniform(nbr_g[ea]) : g1;
     }
