@@ -75,6 +75,28 @@ def test_chi_tau_tiny_workload(precision, oracle_cache):
     assert err <= CHI_TOL[precision]
 
 
+@pytest.mark.parametrize("case", ["cfg0", "micro1"])
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_chi_tau_block_order(case, precision, oracle_cache):
+    """The plan groups each atom's LRI blocks by neighbour atom itself (the fused kernels walk
+    the periodic images of one neighbour atom together): the same blocks passed in a random
+    order (permuted block list over the same C buffer) give chi within the same bar."""
+    import dataclasses
+    inp, key = (cfg(0), "cfg0") if case == "cfg0" else (micro(**MICRO[1]), ("micro", 1))
+    b = inp.blocks
+    perm = np.random.default_rng(1234).permutation(len(b.I))
+    shuffled = dataclasses.replace(inp, blocks=dataclasses.replace(
+        b, I=b.I[perm], K=b.K[perm], R=b.R[perm], d=b.d[perm], off=b.off[perm]))
+    say("case chi_tau block order", case, precision, "blocks", len(perm))
+    ref = _oracle_chi(inp, key, oracle_cache)
+    chi, _, _ = gpu_chi_tau(shuffled, precision)
+    got = chi.cpu().numpy()
+    err = rel(got, ref)
+    say("  rel err", err)
+    assert np.all(np.isfinite(got))
+    assert err <= CHI_TOL[precision]
+
+
 @pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
 def test_tau_rescale_is_exact(precision):
     """G scaled by 2^-80: without the per-tau power-of-two scale the FP32 products (~1e-54) would
