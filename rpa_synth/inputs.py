@@ -163,9 +163,9 @@ def lri_blocks(cell: Cell, I, K, R, d, margin):
     return LRIBlocks(I, K, R, d, off, C, margin)
 
 
-def coulomb(cell: Cell, nauxtot, nq):
+def coulomb(cell: Cell, nauxtot, nq, note=None):
     """v(q) = s (L L^H + 1e-3 I) / lambda_max(L L^H + 1e-3 I), L complex Gaussian with
-    Re, Im ~ N(0, 1/2); s = cell.v_scale."""
+    Re, Im ~ N(0, 1/2); s = cell.v_scale.  note, if given, is called after each q."""
     rng = rng_for(cell.seed_key, Q_COULOMB)
     vq = np.empty((nq, nauxtot, nauxtot), dtype=np.complex128)
     for q in range(nq):
@@ -173,6 +173,8 @@ def coulomb(cell: Cell, nauxtot, nq):
         v = L @ L.conj().T + 1e-3 * np.eye(nauxtot)
         v = 0.5 * (v + v.conj().T)
         vq[q] = v * (cell.v_scale / _lambda_max(v))
+        if note:
+            note("coulomb q %d of %d" % (q + 1, nq))
     return vq
 
 
@@ -187,7 +189,10 @@ def _lambda_max(v):
                        return_eigenvectors=False)[0])
 
 
-def make_inputs(cell: Cell, with_coulomb=True, keep_wfc=True, with_green=True) -> Inputs:
+def make_inputs(cell: Cell, with_coulomb=True, keep_wfc=True, with_green=True, progress=None) -> Inputs:
+    """All seeded inputs of one cell.  progress, if given, is called with the name of each
+    stage as it finishes (large cells take minutes)."""
+    note = progress or (lambda stage: None)
     I, K, R, d, margin = lat.neighbour_pairs(cell.lattice, cell.frac, cell.rcut)
     nao, naux = cell.nao, cell.naux
     nb, nauxtot = int(nao.sum()), int(naux.sum())
@@ -197,6 +202,7 @@ def make_inputs(cell: Cell, with_coulomb=True, keep_wfc=True, with_green=True) -
     hb = hopping_blocks(cell, I, K, R, d)
     H = bloch_hamiltonian(cell, I, K, R, hb, kfrac)
     eps, wfc = np.linalg.eigh(H)
+    note("bands")
     nocc = nb // 2
     vbm = eps[:, nocc - 1].max()
     cbm = eps[:, nocc].min()
@@ -206,9 +212,12 @@ def make_inputs(cell: Cell, with_coulomb=True, keep_wfc=True, with_green=True) -
     emin = GAP
     emax = float(eps.max() - eps.min())
     g = make_grids(cell.ntau, emin, emax)
+    note("grids")
     Gocc, Gun = green_functions(eps, wfc, nocc, mu, g["tau"], kfrac, Rvec) if with_green else (None, None)
+    note("green functions")
     blocks = lri_blocks(cell, I, K, R, d, margin)
-    vq = coulomb(cell, nauxtot, len(kfrac)) if with_coulomb else None
+    note("LRI blocks")
+    vq = coulomb(cell, nauxtot, len(kfrac), note) if with_coulomb else None
     return Inputs(cell=cell, nao=nao, naux=naux, ao_off=lat.offsets(nao), aux_off=lat.offsets(naux),
                   nb=nb, nauxtot=nauxtot, Rvec=Rvec, kfrac=kfrac, blocks=blocks,
                   eps=eps if keep_wfc else None, wfc=wfc if keep_wfc else None, nocc=nocc, mu=mu,

@@ -189,3 +189,75 @@ def test_sheet_gamma_fullsize():
         del chi
         torch.cuda.synchronize()
         assert eb <= blk_tol and whole <= 1e-5 and de <= 1e-6
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(1200)
+def test_sheet_2x2x1_fullsize():
+    """75-atom sheet plus triatomic on the 2x2x1 mesh (4 lattice vectors, 24 tau, 12 A cutoff):
+    sampled blocks (R = 0 and R != 0) against the oracle, both mixed paths against FP64 over
+    the whole tensor, and E_c of the mixed paths within 1e-6 Ha/atom of the FP64 GPU path.
+    One chi(R, tau) is 42.5 GB in FP64, so the tensors are compared while the FP64 one is
+    resident and each path is built again for its energy after it is freed (peak about 210 GB
+    of device memory)."""
+    import torch
+    torch.cuda.empty_cache()   # blocks cached by the earlier tests of this process
+    from paper_2407_19930_amd import Context, chi0_R_to_q, chi0_tau_to_omega, rpa_correlation_energy, \
+        rpa_ec_workspace_size
+    from rpa_synth.configs import sheet_cell
+    from rpa_synth import make_inputs
+    say("case sheet 2x2x1 full size: generating inputs")
+    inp = make_inputs(sheet_cell((2, 2, 1)), with_coulomb=True, progress=lambda st: say("  inputs: " + st))
+    say("case sheet 2x2x1 full size: natoms %d nb %d naux %d nR %d blocks %d"
+        % (inp.natoms, inp.nb, inp.nauxtot, inp.nR, len(inp.blocks.I)))
+    samples = [(0, 0, 1, 0), (0, 3, 40, 1), (0, 10, 73, 3), (23, 74, 5, 2), (23, 72, 72, 0)]
+    alg = ochi.Alg1(inp)
+    d = device_inputs(inp)
+    ctx = Context(0)
+    N, nw, nq = inp.nauxtot, len(inp.omega), len(inp.kfrac)
+    vq = torch.from_numpy(inp.vq).cuda()
+
+    def energy(chi):
+        ws = torch.empty(rpa_ec_workspace_size(N, nq, nw), dtype=torch.uint8, device="cuda")
+        chi_w = torch.empty((nw, inp.nR, N, N), dtype=torch.float64, device="cuda")
+        chi0_tau_to_omega(ctx, inp.gamma_cos, chi, chi_w)
+        chi_q = torch.empty((nw, nq, N, N), dtype=torch.complex128, device="cuda")
+        chi0_R_to_q(ctx, inp.cell.mesh, inp.kfrac, chi_w, chi_q)
+        del chi_w
+        ec, _ = rpa_correlation_energy(ctx, inp.womega, chi_q, vq, ws)
+        del chi_q, ws
+        torch.cuda.synchronize()
+        return ec
+
+    def whole(chi, ref):
+        num = den = 0.0
+        for t in range(inp.ntau):
+            num += float(((chi[t] - ref[t]).norm() ** 2).item())
+            den += float((ref[t].norm() ** 2).item())
+        return (num / den) ** 0.5
+
+    chi64, _, _ = gpu_chi_tau(inp, "fp64", ctx=ctx, dev_in=d)
+    e64 = _blocks(inp, chi64, samples, alg)
+    say("  fp64 worst block %.3g" % e64)
+    assert e64 <= 1e-11
+    for prec, blk_tol in (("fp32", 1e-5), ("bf16x3", 3e-5)):
+        chi, _, _ = gpu_chi_tau(inp, prec, ctx=ctx, dev_in=d)
+        eb = _blocks(inp, chi, samples, alg)
+        w = whole(chi, chi64)
+        say("  %s worst block %.3g, whole tensor vs fp64 %.3g" % (prec, eb, w))
+        del chi
+        torch.cuda.synchronize()
+        assert eb <= blk_tol and w <= 1e-5
+    ec64 = energy(chi64)
+    del chi64
+    torch.cuda.synchronize()
+    say("  fp64 E_c/atom %.12g" % (ec64 / inp.natoms))
+    assert ec64 < 0
+    for prec in ("fp32", "bf16x3"):
+        chi, _, _ = gpu_chi_tau(inp, prec, ctx=ctx, dev_in=d)
+        ec = energy(chi)
+        del chi
+        torch.cuda.synchronize()
+        de = abs(ec - ec64) / inp.natoms
+        say("  %s E_c/atom %.12g, dE/atom %.3g" % (prec, ec / inp.natoms, de))
+        assert de <= 1e-6
