@@ -47,6 +47,7 @@ def parse():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3", "fp64"])
     ap.add_argument("--workload", type=int, default=1,
                     help="workload index (1: 8-atom diamond-like cell, 2: 32-atom two-species cell, "
+                         "3: 75-atom sheet with a triatomic at Gamma, "
                          "4: 64 serving cells in one graph)")
     ap.add_argument("--lanes", type=int, default=8, help="concurrent lanes of the serving batch (workload 4)")
     ap.add_argument("--gen-workers", type=int, default=16, help="processes generating the serving cells")
