@@ -120,7 +120,7 @@ struct rpa_plan {
   std::vector<int> cp_stride;                   // per atom: packed row length, nao*naux rounded up to 8
   int nbp = 0;                                  // nb rounded up to 8
   long long cp_elems = 0, maxblk = 0;
-  std::vector<int> nbr_start, nbr_K, nbr_R1;
+  std::vector<int> nbr_start, nbr_K, nbr_R1, nbr_run_end;
   std::vector<long long> nbr_cp, nbr_cb;
   std::vector<int> nslices;                     // per atom U: sum of n_K over its neighbours
   std::vector<int> rows_start;
@@ -657,6 +657,11 @@ int rpa_plan_create(rpa_ctx *ctx, const rpa_cell *cell, const rpa_lri_blocks *bl
     p->nbr_cp[e] = p->out_off[b];
     p->nbr_cb[e] = p->cb_off[b];
   }
+  // end of the run of entries with the same atom K that holds entry e (the fused kernels' walk)
+  p->nbr_run_end.resize(nblk);
+  for (int a = 0; a < na; ++a)
+    for (int e = p->nbr_start[a + 1] - 1; e >= p->nbr_start[a]; --e)
+      p->nbr_run_end[e] = e + 1 < p->nbr_start[a + 1] && p->nbr_K[e + 1] == p->nbr_K[e] ? p->nbr_run_end[e + 1] : e + 1;
   p->nslices.assign(na, 0);
   for (int a = 0; a < na; ++a)
     for (int e = p->nbr_start[a]; e < p->nbr_start[a + 1]; ++e) p->nslices[a] += p->nao[p->nbr_K[e]];
@@ -818,6 +823,7 @@ int rpa_plan_create(rpa_ctx *ctx, const rpa_cell *cell, const rpa_lri_blocks *bl
                s_aoo = add(p->ao_off.data(), na * 4), s_auxo = add(p->aux_off.data(), na * 4),
                s_aoa = add(p->atom_of_ao.data(), p->nb * 4), s_ns = add(p->nbr_start.data(), (na + 1) * 4),
                s_nK = add(p->nbr_K.data(), nblk * 4), s_nR1 = add(p->nbr_R1.data(), nblk * 4),
+               s_nre = add(p->nbr_run_end.data(), nblk * 4),
                s_ncp = add(p->nbr_cp.data(), nblk * 8), s_rs = add(p->rows_start.data(), (na + 1) * 4),
                s_ri = add(p->row_info.data(), p->row_info.size() * 16), s_noff = add(p->noff.data(), p->noff.size() * 8),
                s_tV = add(p->tileV.data(), p->tileV.size() * 4), s_tM = add(p->tileM.data(), p->tileM.size() * 4),
@@ -861,6 +867,7 @@ int rpa_plan_create(rpa_ctx *ctx, const rpa_cell *cell, const rpa_lri_blocks *bl
   tb.nbr_start = I32(s_ns);
   tb.nbr_K = I32(s_nK);
   tb.nbr_R1 = I32(s_nR1);
+  tb.nbr_run_end = I32(s_nre);
   tb.nbr_cp = I64(s_ncp);
   tb.rows_start = I32(s_rs);
   tb.row_info = (const int4 *)(d + secs[s_ri].off);

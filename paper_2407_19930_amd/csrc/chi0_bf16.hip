@@ -115,9 +115,7 @@ __global__ __launch_bounds__(FB_THREADS) void fused_bf16_kernel(Chi0Tables tb, P
     nbr_k[e] = tb.nao[K];
     nbr_c[e] = tb.nbr_cb[e0 + e];
     nbr_n[e] = tb.noff[((size_t)V * natoms + K) * nR + tb.bvk.sub(tb.nbr_R1[e0 + e], R)];
-    int f = e + 1;
-    while (f < ne && tb.nbr_K[e0 + f] == K) ++f;
-    nbr_g[e] = f;   // end of the run of entries with the same atom K
+    nbr_g[e] = tb.nbr_run_end[e0 + e] - e0;   // end of the run of entries with the same atom K
   }
 
   // A operand of the O GEMM, split: A[i][j'] = G^un_ij(R) for j' = j < n_V, G^occ_ij(R) for

@@ -11,6 +11,7 @@ struct Chi0Tables {
   // neighbourhood N[U] (CSR over first atom U): entry e = block with I = U
   const int *nbr_start;                       // [natoms + 1]
   const int *nbr_K, *nbr_R1;                  // [nblk] second atom, folded lattice vector
+  const int *nbr_run_end;                     // [nblk] end of the run of entries with the same K
   const long long *nbr_cp;                    // [nblk] offset of the packed block [k][i][mu]
   const long long *nbr_cb;                    // [nblk] offset of the split-BF16 block (BF16X3 plans)
   const int *nslices;                         // [natoms] sum of nao[K] over the neighbours of U

@@ -408,9 +408,7 @@ __global__ __launch_bounds__(FU_THREADS) void fused_kernel(Chi0Tables tb, PairIt
     nbr_k[e] = tb.nao[K];
     nbr_c[e] = tb.nbr_cp[e0 + e];
     nbr_n[e] = tb.noff[((size_t)V * natoms + K) * nR + tb.bvk.sub(tb.nbr_R1[e0 + e], R)];
-    int f = e + 1;
-    while (f < ne && tb.nbr_K[e0 + f] == K) ++f;
-    nbr_g[e] = f;   // end of the run of entries with the same atom K
+    nbr_g[e] = tb.nbr_run_end[e0 + e] - e0;   // end of the run of entries with the same atom K
   }
   for (int e = tid; e < 2 * kMaxNaux * IP + 4; e += FU_THREADS) Cs[e] = T(0);
 
