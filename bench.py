@@ -3,13 +3,18 @@
 
 A step is one pass of the whole path on device-resident inputs:
   build_chi0_tau -> chi0_tau_to_omega -> chi0_R_to_q -> rpa_correlation_energy.
-Workload: the 8-atom diamond-like cell (a = 5.4 A, 4x4x4 k-mesh, 26 NAO / 100 ABF per atom,
-16 tau/omega points, 10 A cutoff), seeded synthetic inputs.
+Default workload: the largest single-GPU cell, a 72-atom hexagonal sheet (a = 2.46 A, 26 NAO / 100 ABF
+per atom) with a bent triatomic 3 A above it (26/120 and 2 x 13/60), 15 A of vacuum, Gamma point,
+24 tau/omega points, 12 A cutoff, on the split-BF16 (3-term) path; seeded synthetic inputs.  The
+2x2x1 k-mesh of the same cell (`--workload sheet2x2x1`) quadruples every stage and does not fit
+the default 20 + 5 steps into a ten-minute run, so it is a separate command.
 
 Prints one JSON line.  `value` is the algorithmic flop count of the chi0 build (Algorithm 1
 with its N intermediate evaluated once per (V, K, R1-R)) divided by the wall time of the whole
-step, in TFLOP/s.  The same inputs run once through the FP64 path (outside the timed region)
-for the chi0 and E_c errors of the mixed path.  The cpu_baseline leg times the FP64 oracle on
+step, in TFLOP/s.  The same inputs run through the FP64 path (one untimed and one timed step,
+outside the timed region) for the chi0 and E_c errors of the mixed path and for its build rate
+and E_c time; the `gate` field says whether the mixed result meets the accuracy bars
+(|dE_c| <= 1e-6 Ha/atom, relative chi0 Frobenius error <= 1e-5 against FP64).  The cpu_baseline leg times the FP64 oracle on
 a bounded sample of the same workload on the host cores.
 """
 from __future__ import annotations
@@ -39,19 +44,23 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+WORKLOADS = {"tiny": 0, "diamond8": 1, "twospecies32": 2, "sheet": 3, "sheet2x2x1": 33, "serving": 4}
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3", "fp64"])
-    ap.add_argument("--workload", type=int, default=1,
-                    help="workload index (1: 8-atom diamond-like cell, 2: 32-atom two-species cell, "
-                         "3: 75-atom sheet with a triatomic at Gamma, "
-                         "4: 64 serving cells in one graph)")
-    ap.add_argument("--lanes", type=int, default=8, help="concurrent lanes of the serving batch (workload 4)")
+    ap.add_argument("--precision", default="bf16x3", choices=["fp32", "bf16x3", "fp64"])
+    ap.add_argument("--workload", default="sheet",
+                    help="workload: sheet (75-atom sheet + triatomic at Gamma, the default), sheet2x2x1 (the same "
+                         "cell on a 2x2x1 k-mesh), diamond8 (8-atom diamond-like cell, 4x4x4), twospecies32 "
+                         "(32-atom two-species cell, 3x3x1), serving (64 cells in one graph), tiny; or the "
+                         "index 0-4 (33 = sheet2x2x1)")
+    ap.add_argument("--lanes", type=int, default=8, help="concurrent lanes of the serving batch")
     ap.add_argument("--gen-workers", type=int, default=16, help="processes generating the serving cells")
-    ap.add_argument("--ncells", type=int, default=64, help="serving cells used (workload 4; the first n of 64)")
+    ap.add_argument("--ncells", type=int, default=64, help="serving cells used (the first n of 64)")
     ap.add_argument("--no-fp64-check", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tuning", default="auto",
@@ -60,7 +69,51 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a plain 1 GiB device copy first (reference dispatch for the byte counters)")
-    return ap.parse_args()
+    a = ap.parse_args()
+    a.workload = WORKLOADS[a.workload] if a.workload in WORKLOADS else int(a.workload)
+    if a.workload not in WORKLOADS.values():
+        ap.error("unknown workload %r" % a.workload)
+    return a
+
+
+def host_info():
+    """Host CPU description for the cpu_baseline record: model name, logical CPUs the OS
+    reports, CPUs this process may run on, and the BLAS threads numpy uses."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        affinity = os.cpu_count()
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([t.get("num_threads", 0) for t in threadpool_info()] + [1])
+    except Exception:
+        threads = affinity
+    return {"cpu_model": model, "os_cpu_count": os.cpu_count(), "cpus_usable": affinity, "blas_threads": threads}
+
+
+def recorded_counters(kernel, precision, workload):
+    """MFMA-busy fraction of a kernel from the committed counter summary (a line
+    `mfma_busy <kernel> <precision> <workload> <fraction> <hash>`), or None when absent or taken
+    with other kernel sources."""
+    path = os.path.join(ROOT, "profiles", "pmc_%s_%s_%s.md" % (kernel, workload, precision))
+    if not os.path.exists(path):
+        return None
+    cur = kernel_source_hash()
+    with open(path) as fh:
+        for line in fh:
+            f = line.strip().strip("`").split()
+            if len(f) == 6 and f[0] == "mfma_busy" and f[1:4] == [kernel, precision, workload]:
+                return float(f[4]) if f[5] == cur else None
+    return None
 
 
 def kernel_source_hash():
@@ -132,11 +185,7 @@ def cpu_baseline(inp, budget_s):
     """Time the FP64 oracle (Algorithm 1) on a bounded sample: tau_0, atom V = 0, its N
     intermediate for every (K, dR), then blocks (U, V=0, R) until the time budget is spent."""
     from oracle import chi0 as ochi
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([t.get("num_threads", 0) for t in threadpool_info()] + [1])
-    except Exception:
-        threads = os.cpu_count()
+    host = host_info()
     alg = ochi.Alg1(inp)
     nao, naux, nR, nb = inp.nao, inp.naux, inp.nR, inp.nb
     S = [sum(nao[inp.blocks.K[b]] for b in alg.nbrs[a]) for a in range(inp.natoms)]
@@ -154,9 +203,10 @@ def cpu_baseline(inp, budget_s):
             flops += 2.0 * 2.0 * nU * aV * nV * S[V] + 8.0 * nU * nV * aV * S[U] + 2.0 * aU * aV * nU * S[U]
             nblk += 1
     dt = time.perf_counter() - t0
-    return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": int(threads), "kind": "oracle",
+    return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": int(host["blas_threads"]), "kind": "oracle",
             "sample": "tau_0, N intermediate of atom 0 for all (K, dR), then %d blocks (U, V=0, R) of "
-                      "Algorithm 1; %.1f s, %.3g algorithmic flops" % (nblk, dt, flops)}
+                      "Algorithm 1; %.1f s, %.3g algorithmic flops" % (nblk, dt, flops),
+            "host": host}
 
 
 def _gen_cell(cell):
@@ -258,14 +308,20 @@ def serving_main(args):
     print(json.dumps(rec))
 
 
+def gate(chi_err, dEc):
+    """Accuracy bars of the mixed path against the FP64 path on the same inputs."""
+    return {"chi_rel_err_vs_fp64": chi_err, "dEc_per_atom_vs_fp64": dEc, "chi_bar": 1e-5, "dEc_bar": 1e-6,
+            "pass": bool(chi_err <= 1e-5 and dEc <= 1e-6)}
+
+
 def main():
     args = parse()
-    if args.workload == 4 and args.gpus == 1:
-        return serving_main(args)
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the path is measured on one MI355X "
               "(multi-GPU sharding is a design note only); use --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.workload == 4:
+        return serving_main(args)
     import torch
     from paper_2407_19930_amd import (Context, Plan, build_chi0_tau, chi0_R_to_q, chi0_tau_to_omega,
                                       rpa_correlation_energy, rpa_ec_workspace_size)
@@ -283,9 +339,10 @@ def main():
     C = torch.from_numpy(inp.blocks.C).to(dev)
     vq = torch.from_numpy(inp.vq).to(dev)
     N, nR, nt, nw, nq = inp.nauxtot, inp.nR, inp.ntau, len(inp.omega), len(inp.kfrac)
-    chi_tau = torch.empty((nt, nR, N, N), dtype=torch.float64, device=dev)
+    # chi(tau) and chi(q, i omega) share one buffer: chi(tau) is dead once chi(i omega) exists
+    big = torch.empty(max(nt * nR, 2 * nw * nq) * N * N, dtype=torch.float64, device=dev)
+    chi_tau = big[:nt * nR * N * N].view(nt, nR, N, N)
     chi_w = torch.empty((nw, nR, N, N), dtype=torch.float64, device=dev)
-    chi_q = torch.empty((nw, nq, N, N), dtype=torch.complex128, device=dev)
     ws_ec = torch.empty(rpa_ec_workspace_size(N, nq, nw), dtype=torch.uint8, device=dev)
     ctx = Context(0)
     b = inp.blocks
@@ -302,24 +359,47 @@ def main():
         p = Plan(ctx, inp.nao, inp.naux, cell.mesh, b.I, b.K, b.R, b.off, nt, prec)
         return p, torch.empty(max(p.workspace_bytes, 1), dtype=torch.uint8, device=dev)
 
-    def step(plan, ws):
+    def chi_q_view():
+        return big[:2 * nw * nq * N * N].view(torch.complex128).view(nw, nq, N, N)
+
+    def step(plan, ws, keep_chi=None):
         build_chi0_tau(plan, inp.spin_factor, Gocc, Gun, C, ws, chi_tau)
+        if keep_chi is not None:
+            keep_chi.copy_(chi_tau)
         chi0_tau_to_omega(ctx, inp.gamma_cos, chi_tau, chi_w)
-        chi0_R_to_q(ctx, cell.mesh, inp.kfrac, chi_w, chi_q)
-        return rpa_correlation_energy(ctx, inp.womega, chi_q, vq, ws_ec)
+        cq = chi_q_view()
+        chi0_R_to_q(ctx, cell.mesh, inp.kfrac, chi_w, cq)
+        return rpa_correlation_energy(ctx, inp.womega, cq, vq, ws_ec)
+
+    build_kernels = ("pack_c", "pad_g", "nstage", "fused")
+    ec_kernels = ("cos_transform", "r2q", "ec_stage")
+
+    def read_profile(steps):
+        kt = {k: ctx.profile_read(k) for k in build_kernels + ec_kernels}
+        return (kt, sum(kt[k][0] for k in build_kernels) / steps, sum(kt[k][0] for k in ec_kernels) / steps)
 
     extra = {}
+    fp64 = None
+    chi64 = None
     if not args.no_fp64_check and args.precision != "fp64":
         p64, ws64 = make_plan("fp64")
+        chi64 = torch.empty_like(chi_tau)
+        step(p64, ws64, chi64)                      # untimed
         torch.cuda.synchronize()
+        ctx.profile(True)
         t0 = time.perf_counter()
         ec64, _ = step(p64, ws64)
         torch.cuda.synchronize()
         t64 = time.perf_counter() - t0
-        chi64 = chi_tau.clone()
-        log("fp64 reference step %.2f s, E_c/atom %.12g" % (t64, ec64 / inp.natoms))
+        _, b64, e64 = read_profile(1)
+        ctx.profile(False)
+        a64, _ = p64.flops()
+        log("fp64 reference step %.2f s (build %.0f ms, E_c stage %.0f ms), E_c/atom %.12g"
+            % (t64, b64, e64, ec64 / inp.natoms))
         del ws64, p64
-        extra["fp64_ms_per_step"] = t64 * 1e3
+        torch.cuda.empty_cache()
+        fp64 = {"ms_per_step": t64 * 1e3, "build_ms": b64, "build_tflops": a64 / (b64 * 1e-3) / 1e12,
+                "ec_time_ms": e64, "Ec_per_atom": ec64 / inp.natoms}
     plan, ws = make_plan(args.precision)
     alg_flops, exec_flops = plan.flops()
     if args.tuning == "auto":
@@ -340,11 +420,14 @@ def main():
         log("timed step %d done" % i)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
-    kt = {k: ctx.profile_read(k) for k in ("pack_c", "pad_g", "nstage", "fused", "cos_transform", "r2q",
-                                           "ec_stage")}
+    kt, build_ms, ec_ms = read_profile(args.steps)
     ctx.profile(False)
-    build_ms = sum(kt[k][0] for k in ("pack_c", "pad_g", "nstage", "fused")) / args.steps
-    ec_ms = sum(kt[k][0] for k in ("cos_transform", "r2q", "ec_stage")) / args.steps
+    if chi64 is not None:
+        # one more build for the chi(tau) error (the timed steps overwrite chi(tau) with chi(q))
+        build_chi0_tau(plan, inp.spin_factor, Gocc, Gun, C, ws, chi_tau)
+        torch.cuda.synchronize()
+        chi_err = float(torch.linalg.vector_norm(chi_tau - chi64) / torch.linalg.vector_norm(chi64))
+        del chi64
 
     # the Green's functions of the step's input, built on the GPU from the eigenpairs (outside the
     # timed steps, which take G as given): one untimed and one timed call
@@ -356,9 +439,10 @@ def main():
     dom = max(("nstage", "fused"), key=lambda k: kt[k][0])
     stage = 0 if dom == "nstage" else 1
     st_alg, st_exec = plan.stage_flops(stage)
-    per_launch = st_alg / nt
     avg_ms = kt[dom][0] / max(kt[dom][1], 1)
-    achieved = per_launch / (avg_ms * 1e-3) / 1e12
+    launches_per_step = kt[dom][1] / args.steps
+    achieved = st_alg / launches_per_step / (avg_ms * 1e-3) / 1e12
+    executed = st_exec / launches_per_step / (avg_ms * 1e-3) / 1e12
     # split-BF16 kernels are priced against the FP32-equivalent split-BF16 peak; a BF16X3 plan too
     # large for the split-BF16 N stage runs the FP32 one (it then has a K-step choice)
     if args.precision == "bf16x3":
@@ -368,13 +452,22 @@ def main():
         peak = PEAK_TFLOPS[args.precision]
     roofline = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                 "traffic": recorded_traffic(dom, args.precision, cell.name, tuning), "kernel": dom,
-                "executed_tflops": st_exec / nt / (avg_ms * 1e-3) / 1e12}
+                "launches_per_step": launches_per_step, "avg_launch_ms": avg_ms,
+                "executed_achieved": executed, "executed_frac": executed / peak,
+                "mfma_busy": recorded_counters(dom, args.precision, cell.name)}
+    other = "fused" if dom == "nstage" else "nstage"
+    o_alg, o_exec = plan.stage_flops(1 - stage)
+    o_ms = kt[other][0] / args.steps
+    extra["other_kernel"] = {"kernel": other, "ms_per_step": o_ms,
+                             "achieved": o_alg / (o_ms * 1e-3) / 1e12 if o_ms > 0 else None,
+                             "frac": o_alg / (o_ms * 1e-3) / 1e12 / peak if o_ms > 0 else None}
 
-    if not args.no_fp64_check and args.precision != "fp64":
-        d = chi_tau - chi64
-        extra["chi_rel_err_vs_fp64"] = float(torch.linalg.vector_norm(d) / torch.linalg.vector_norm(chi64))
-        extra["dEc_per_atom_vs_fp64"] = abs(ec - ec64) / inp.natoms
-        extra["speedup_vs_fp64"] = extra["fp64_ms_per_step"] / (dt * 1e3)
+    if fp64 is not None:
+        dEc = abs(ec - fp64["Ec_per_atom"] * inp.natoms) / inp.natoms
+        extra["gate"] = gate(chi_err, dEc)
+        extra["fp64"] = fp64
+        extra["speedup_vs_fp64"] = fp64["ms_per_step"] / (dt * 1e3)
+        extra["build_speedup_vs_fp64"] = fp64["build_ms"] / build_ms
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(inp, args.cpu_seconds)
