@@ -243,6 +243,21 @@ RPA_API int rpa_correlation_energy(rpa_ctx *ctx, int n, int nq, int nomega, cons
                            const double *chi0_q, const double *v_q, void *workspace,
                            size_t workspace_bytes, double *Ec, double *Ec_q);
 
+/* Energy stage without device allocation, for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the same result
+ * as rpa_correlation_energy (same kernels, same order), with its workspace taken from a device
+ * array of rpa_noalloc_scratch_bytes() = 64 MiB that the library holds on every GPU it runs on
+ * until the process ends.  No hipMalloc, hipFree or other allocation happens in the call.
+ *   n, nq, nomega, womega, chi0_q, v_q, Ec, Ec_q : as rpa_correlation_energy
+ * Sizes whose energy-stage workspace (with one (q, omega) matrix per batch) exceeds the scratch
+ * are rejected with RPA_ERR_WORKSPACE.  Every call on one GPU shares that GPU's scratch and
+ * leaves its contents behind; calls that overlap on one GPU (several streams or host threads)
+ * race and must be serialised by the caller.  Synchronises the context's stream.
+ * Errors: RPA_ERR_ARG, RPA_ERR_WORKSPACE, RPA_ERR_NOT_HPD, RPA_ERR_NONFINITE, RPA_ERR_HIP. */
+RPA_API size_t rpa_noalloc_scratch_bytes(void);
+RPA_API int rpa_correlation_energy_noalloc(rpa_ctx *ctx, int n, int nq, int nomega, const double *womega,
+                                           const double *chi0_q, const double *v_q, double *Ec, double *Ec_q);
+
 /* ---- Batches of independent cells -------------------------------------------
  * The whole path (build_chi0_tau, chi0_tau_to_omega, chi0_R_to_q and the energy
  * stage of rpa_correlation_energy) of many cells, captured once into one HIP graph

@@ -25,7 +25,8 @@ EXPORTED = ["rpa_create", "rpa_set_stream", "rpa_destroy", "rpa_last_error", "rp
             "build_chi0_tau", "chi0_tau_to_omega", "chi0_R_to_q", "rpa_ec_workspace_size",
             "rpa_correlation_energy", "rpa_batch_create", "rpa_batch_run", "rpa_batch_result",
             "rpa_batch_destroy", "rpa_plan_autotune", "rpa_plan_get_tuning", "rpa_plan_set_tuning",
-            "rpa_green_workspace_size", "build_green_tau"]
+            "rpa_green_workspace_size", "build_green_tau", "rpa_noalloc_scratch_bytes",
+            "rpa_correlation_energy_noalloc"]
 
 
 class RpaError(RuntimeError):
@@ -98,6 +99,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.rpa_green_workspace_size.restype = sz
     lib.build_green_tau.argtypes = [vp, i, i, i, dp, i, vp, ctypes.POINTER(ctypes.c_int), vp, vp, vp, vp, sz, vp, vp]
     lib.rpa_correlation_energy.argtypes = [vp, i, i, i, vp, vp, vp, vp, sz, ctypes.POINTER(dp), vp]
+    lib.rpa_noalloc_scratch_bytes.argtypes = []
+    lib.rpa_noalloc_scratch_bytes.restype = sz
+    lib.rpa_correlation_energy_noalloc.argtypes = [vp, i, i, i, vp, vp, vp, ctypes.POINTER(dp), vp]
     lib.rpa_batch_create.argtypes = [vp, i, i, ctypes.POINTER(_BatchCell), ctypes.POINTER(vp)]
     lib.rpa_batch_run.argtypes = [vp]
     lib.rpa_batch_result.argtypes = [vp, vp, vp]
@@ -106,7 +110,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.rpa_plan_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
     lib.rpa_plan_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
     for name in EXPORTED:
-        if name not in ("rpa_destroy", "rpa_last_error", "rpa_ec_workspace_size", "rpa_green_workspace_size"):
+        if name not in ("rpa_destroy", "rpa_last_error", "rpa_ec_workspace_size", "rpa_green_workspace_size",
+                        "rpa_noalloc_scratch_bytes"):
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -338,6 +343,26 @@ def rpa_correlation_energy(ctx: Context, womega, chi0_q, v_q, workspace):
                                              _dev(vq, torch.float64), _dev(workspace),
                                              workspace.numel() * workspace.element_size(), ctypes.byref(ec),
                                              ecq.ctypes.data_as(ctypes.c_void_p)))
+    return ec.value, ecq
+
+
+def rpa_noalloc_scratch_bytes() -> int:
+    return int(load().rpa_noalloc_scratch_bytes())
+
+
+def rpa_correlation_energy_noalloc(ctx: Context, womega, chi0_q, v_q):
+    """As rpa_correlation_energy, with the library's own device scratch instead of a workspace
+    (no device allocation in the call).  Returns (E_c per cell, per-q contributions)."""
+    import torch
+    w, wp = _host(womega, np.float64)
+    cq = torch.view_as_real(chi0_q) if chi0_q.dtype == torch.complex128 else chi0_q
+    vq = torch.view_as_real(v_q) if v_q.dtype == torch.complex128 else v_q
+    nomega, nq, n = chi0_q.shape[0], chi0_q.shape[1], chi0_q.shape[2]
+    ec = ctypes.c_double()
+    ecq = np.zeros(nq)
+    ctx.check(ctx.lib.rpa_correlation_energy_noalloc(ctx.h, n, nq, nomega, wp, _dev(cq, torch.float64),
+                                                     _dev(vq, torch.float64), ctypes.byref(ec),
+                                                     ecq.ctypes.data_as(ctypes.c_void_p)))
     return ec.value, ecq
 
 

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <tuple>
 #include <cstdio>
 #include <cstring>
@@ -36,6 +37,8 @@ struct rpa_ctx {
   std::map<std::string, std::pair<double, int>> totals;
   // autotuner choices by plan shape class and device architecture
   std::map<std::string, rpa_tuning> tune_cache;
+  // device address of the no-allocation scratch array on this context's device
+  void *scratch = nullptr;
 };
 
 namespace {
@@ -55,6 +58,8 @@ int fail(rpa_ctx *ctx, int code, const std::string &msg) {
   } while (0)
 
 size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+hipError_t scratch_setup(int device, void **out);   // device scratch of the no-allocation entry point
 
 // Records HIP events around the enclosed launches when profiling is on.
 struct Timed {
@@ -512,7 +517,10 @@ int rpa_create(rpa_ctx **out, int device, void *hip_stream) {
   ctx->stream = (hipStream_t)hip_stream;
   hipError_t e = hipSetDevice(device);
   if (e == hipSuccess) e = hipMalloc(&ctx->params, kParamsBytes);
+  // once per device, with the device current: the address of its copy of the scratch array
+  if (e == hipSuccess) e = scratch_setup(device, &ctx->scratch);
   if (e != hipSuccess) {
+    if (ctx->params) hipFree(ctx->params);
     delete ctx;
     return RPA_ERR_HIP;
   }
@@ -1165,6 +1173,79 @@ int rpa_correlation_energy(rpa_ctx *ctx, int n, int nq, int nomega, const double
   *Ec = hecq[nq];
   if (Ec_q)
     for (int q = 0; q < nq; ++q) Ec_q[q] = hecq[q];
+  return RPA_OK;
+}
+
+// ---- energy stage with the library's own device scratch (no allocation) ----
+namespace {
+// Every GPU the library runs on holds one copy of this array until the process ends.  In host
+// code its name is only a stand-in: the device address comes from hipGetSymbolAddress.
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+void *scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on `device`, looked up once per device; the device must be current.
+hipError_t scratch_setup(int device, void **out) {
+  std::lock_guard<std::mutex> lk(scratch_mu);
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  if (!scratch_dev[device]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    scratch_dev[device] = p;
+  }
+  *out = scratch_dev[device];
+  return hipSuccess;
+}
+}  // namespace
+
+size_t rpa_noalloc_scratch_bytes(void) { return kNoAllocScratchBytes; }
+
+int rpa_correlation_energy_noalloc(rpa_ctx *ctx, int n, int nq, int nomega, const double *womega,
+                                   const double *chi0_q, const double *v_q, double *Ec, double *Ec_q) {
+  if (!ctx) return RPA_ERR_ARG;
+  if (!womega || !chi0_q || !v_q || !Ec) return fail(ctx, RPA_ERR_ARG, "null pointer");
+  if (n <= 0 || nq <= 0 || nomega <= 0) return fail(ctx, RPA_ERR_ARG, "sizes must be positive");
+  // the scratch holds the energy-stage layout plus two status words at its end
+  constexpr size_t kStatusBytes = 256;
+  EcLayout l;
+  if (!ec_fit_layout(n, nq, nomega, kNoAllocScratchBytes - kStatusBytes, l))
+    return fail(ctx, RPA_ERR_WORKSPACE,
+                "n = " + std::to_string(n) + ", nq = " + std::to_string(nq) +
+                    " needs more than the 64 MiB device scratch of rpa_correlation_energy_noalloc");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  char *ws = (char *)ctx->scratch;
+  if (!ws) return fail(ctx, RPA_ERR_HIP, "device scratch address was not set up for this context");
+  hipStream_t s = ctx->stream;
+  int *status = (int *)(ws + kNoAllocScratchBytes - kStatusBytes);
+  double *wdev = (double *)(ws + l.w);
+  HIP_TRY(ctx, hipMemcpyAsync(wdev, womega, nomega * 8, hipMemcpyHostToDevice, s));
+  {
+    Timed tm(ctx, "ec_stage");
+    const int rc = ec_enqueue(ctx, s, n, nq, nomega, wdev, chi0_q, v_q, ws, l);
+    if (rc != RPA_OK) return rc;
+    HIP_TRY(ctx, launch_first_flag((const int *)(ws + l.flags), nq + nq * nomega, status, s));
+  }
+  int st[2] = {0, -1};
+  const double *ecq = (const double *)(ws + l.ecq);
+  HIP_TRY(ctx, hipMemcpyAsync(st, status, sizeof(st), hipMemcpyDeviceToHost, s));
+  HIP_TRY(ctx, hipMemcpyAsync(Ec, ecq + nq, sizeof(double), hipMemcpyDeviceToHost, s));
+  if (Ec_q) HIP_TRY(ctx, hipMemcpyAsync(Ec_q, ecq, (size_t)nq * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(ctx, hipStreamSynchronize(s));
+  if (st[0] != 0) {
+    const int idx = st[1];
+    if (idx < nq)
+      return fail(ctx, RPA_ERR_NOT_HPD, "v(q) is not Hermitian positive definite at q index " + std::to_string(idx));
+    const int q = (idx - nq) / nomega, k = (idx - nq) % nomega;
+    if (st[0] == 1)
+      return fail(ctx, RPA_ERR_NOT_HPD, "1 - L^H chi L is not positive definite at q index " + std::to_string(q) +
+                                            ", omega index " + std::to_string(k));
+    return fail(ctx, RPA_ERR_NONFINITE,
+                "non-finite log-determinant at q index " + std::to_string(q) + ", omega index " + std::to_string(k));
+  }
   return RPA_OK;
 }
 

@@ -33,6 +33,8 @@ hipError_t launch_trace_identity_minus(double *B, size_t stride, int n, int batc
 hipError_t launch_logdet(const double *A, size_t stride, int n, int batch, const double *trB, double *f, int *flags,
                          int flag_base, hipStream_t s);
 hipError_t launch_fill_int(int *p, size_t n, int v, hipStream_t s);
+// out[0] = first nonzero of flags[0, n) in index order (0 if none), out[1] = its index (-1 if none)
+hipError_t launch_first_flag(const int *flags, int n, int *out, hipStream_t s);
 hipError_t launch_copy_words(void *dst, const void *src, size_t nwords, hipStream_t s);
 hipError_t launch_quadrature(const double *f, const double *w, int nq, int nomega, double *ecq, hipStream_t s);
 

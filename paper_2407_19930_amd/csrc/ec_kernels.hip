@@ -316,6 +316,26 @@ __global__ __launch_bounds__(256) void quadrature_kernel(const double *f, const 
   }
 }
 
+// First nonzero status flag in index order: out[0] = its value (0 if none), out[1] = its index.
+// One workgroup; each thread scans a strided range, the minimum index wins.
+__global__ __launch_bounds__(256) void first_flag_kernel(const int *flags, int n, int *out) {
+  __shared__ int best[256];
+  int b = n;
+  for (int e = threadIdx.x; e < n; e += blockDim.x)
+    if (flags[e] != 0) {
+      b = e;
+      break;
+    }
+  best[threadIdx.x] = b;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int m = n;
+    for (int i = 0; i < (int)blockDim.x; ++i) m = best[i] < m ? best[i] : m;
+    out[0] = m < n ? flags[m] : 0;
+    out[1] = m < n ? m : -1;
+  }
+}
+
 __global__ void fill_int_kernel(int *p, size_t n, int v) {
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) p[e] = v;
 }
@@ -335,6 +355,11 @@ __global__ void copy_words_kernel(unsigned *__restrict__ dst, const unsigned *__
 }
 
 }  // namespace
+
+hipError_t launch_first_flag(const int *flags, int n, int *out, hipStream_t s) {
+  hipLaunchKernelGGL(first_flag_kernel, dim3(1), dim3(256), 0, s, flags, n, out);
+  return hipGetLastError();
+}
 
 hipError_t launch_fill_int(int *p, size_t n, int v, hipStream_t s) {
   const int blocks = (int)std::min<size_t>((n + 255) / 256, 1024);
