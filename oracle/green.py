@@ -41,9 +41,12 @@ def green_tau(eps, wfc, nocc, mu, tau, kfrac, Rvec):
     for t, tt in enumerate(tau):
         for k in range(nk):
             c = wfc[k]
-            # weights of the occupied and unoccupied bands at this (k, tau)
-            w_occ = np.where(occ, np.exp(-(mu - eps[k]) * tt), 0.0)
-            w_un = np.where(occ, 0.0, np.exp(-(eps[k] - mu) * tt))
+            # weights of the occupied and unoccupied bands at this (k, tau); each exponential is
+            # evaluated on its own channel's bands only (the other channel's would overflow)
+            w_occ = np.zeros(nb)
+            w_un = np.zeros(nb)
+            w_occ[occ] = np.exp(-(mu - eps[k][occ]) * tt)
+            w_un[~occ] = np.exp(-(eps[k][~occ] - mu) * tt)
             P_occ = (c * w_occ[None, :]) @ c.conj().T                     # sum_n c_in w_n c*_jn
             P_un = (c * w_un[None, :]) @ c.conj().T
             for r in range(len(Rvec)):

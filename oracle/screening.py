@@ -135,6 +135,29 @@ def chi0_alg1_screened(inp, theta, taus=None):
     return alg.full(taus), alg.stats
 
 
+def chi0_alg1_screened_pairs(inp, theta, taus=None):
+    """Screened chi over the atom-pair set the method computes (pairs U <= V, Sec. 3.2): every
+    block chi_UV(R) with U <= V from its own keep decisions, and the blocks with U > V from the
+    Hermitian relation chi_VU(-R) = chi_UV(R)^T.  Without screening this is Algorithm 1 again (the
+    relation holds exactly for the full build); with screening the blocks U > V inherit the
+    decisions of their partner.  Returns chi[t, R, mu, nu] and the slice/Z statistics of the
+    U <= V blocks."""
+    alg = ScreenedAlg1(inp, theta)
+    taus = list(range(inp.ntau)) if taus is None else list(taus)
+    out = np.zeros((len(taus), inp.nR, inp.nauxtot, inp.nauxtot))
+    for it, t in enumerate(taus):
+        for U in range(inp.natoms):
+            mu = slice(inp.aux_off[U], inp.aux_off[U] + inp.naux[U])
+            for V in range(U, inp.natoms):
+                nu = slice(inp.aux_off[V], inp.aux_off[V] + inp.naux[V])
+                for R in range(inp.nR):
+                    blk = alg.block(t, U, V, R)
+                    out[it, R, mu, nu] = blk
+                    if V != U:
+                        out[it, int(bvk_sub(0, R, inp.cell.mesh)), nu, mu] = blk.T
+    return out, alg.stats
+
+
 def screening_bound(inp, theta, t):
     """Elementwise bound B[R, mu, nu] on |chi_screened - chi_full| at tau_t from the terms the
     rule drops (see the module docstring)."""

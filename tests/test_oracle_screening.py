@@ -165,3 +165,44 @@ def test_planted_wrong_shift_fails_decomposition(monkeypatch):
     monkeypatch.setattr(scr.ScreenedAlg1, "masks", wrong)
     with pytest.raises(AssertionError):
         test_exact_decomposition_into_dropped_terms(1, 0.2)
+
+
+@pytest.mark.parametrize("idx", range(len(SPECS)))
+def test_pair_set_without_screening_is_algorithm1(idx):
+    """theta = 0 over the pair set U <= V with the Hermitian fill reproduces every block of the
+    full build (independently computed U > V blocks), up to rounding."""
+    inp = micro(**SPECS[idx])
+    full = ochi.chi0_alg1(inp)
+    got, st = scr.chi0_alg1_screened_pairs(inp, 0.0)
+    assert np.abs(got - full).max() <= 1e-13 * np.abs(full).max()
+    npairs = inp.natoms * (inp.natoms + 1) // 2
+    assert st["z_total"] == npairs * inp.nR * inp.ntau == st["z_kept"]
+
+
+@pytest.mark.parametrize("theta", [0.05, 0.2])
+@pytest.mark.parametrize("idx", range(len(SPECS)))
+def test_pair_set_blocks_and_bound(idx, theta):
+    """The U <= V blocks of the pair-set build are the screened blocks themselves, the U > V blocks
+    their transposes at -R, and the whole tensor is within the rigorous bound of the dropped terms
+    (for U > V the transposed bound of the partner)."""
+    inp = micro(**SPECS[idx])
+    mesh = inp.cell.mesh
+    full = ochi.chi0_alg1(inp)
+    got, _ = scr.chi0_alg1_screened_pairs(inp, theta)
+    alg = scr.ScreenedAlg1(inp, theta)
+    scale = np.abs(full).max()
+    for t in range(inp.ntau):
+        B = scr.screening_bound(inp, theta, t)
+        for U in range(inp.natoms):
+            mu = slice(inp.aux_off[U], inp.aux_off[U] + inp.naux[U])
+            for V in range(inp.natoms):
+                nu = slice(inp.aux_off[V], inp.aux_off[V] + inp.naux[V])
+                for R in range(inp.nR):
+                    if U <= V:
+                        assert np.array_equal(got[t, R, mu, nu], alg.block(t, U, V, R))
+                        bound = B[R, mu, nu]
+                    else:
+                        r = int(bvk_sub(0, R, mesh))
+                        assert np.array_equal(got[t, R, mu, nu], got[t, r, nu, mu].T)
+                        bound = B[r, nu, mu].T
+                    assert np.all(np.abs(got[t, R, mu, nu] - full[t, R, mu, nu]) <= bound + 1e-13 * scale)
