@@ -65,7 +65,14 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tuning", default="auto",
                     help="launch variants of the chi0 kernels: 'auto' (rpa_plan_autotune before the warm-up) or "
-                         "NSTAGE_ORDER,NSTAGE_KSTEP,FUSED_ORDER set explicitly (e.g. 0,16,0, the plan defaults)")
+                         "NSTAGE_ORDER,NSTAGE_KSTEP,FUSED_ORDER[,FUSED_SINGLE] set explicitly (e.g. 0,16,0, the plan "
+                         "defaults)")
+    ap.add_argument("--tau-batch", type=int, default=0,
+                    help="tau points per N-stage / fused launch of the timed path (0: as many as keep the "
+                         "per-tau workspace within --tau-batch-gib)")
+    ap.add_argument("--tau-batch-gib", type=float, default=96.0)
+    ap.add_argument("--screening", type=float, default=1e-3,
+                    help="threshold of the extra screened build timed after the steps (0: none)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a plain 1 GiB device copy first (reference dispatch for the byte counters)")
@@ -126,15 +133,18 @@ def kernel_source_hash():
 
 
 def tuning_tag(tuning):
-    """NSTAGE_ORDER,NSTAGE_KSTEP,FUSED_ORDER of a tuning dict (the form --tuning takes)."""
-    return "%d,%d,%d" % (tuning["nstage_order"], tuning["nstage_kstep"], tuning["fused_order"])
+    """NSTAGE_ORDER,NSTAGE_KSTEP,FUSED_ORDER,FUSED_SINGLE of a tuning dict (the form --tuning takes)."""
+    return "%d,%d,%d,%d" % (tuning["nstage_order"], tuning["nstage_kstep"], tuning["fused_order"],
+                            tuning.get("fused_single", 0))
 
 
 def same_variant(kernel, tag_a, tag_b):
     """Whether two tuning tags launch `kernel` alike: the N stage depends on its order and K
-    step, the fused kernel on its item order only."""
+    step, the fused kernel on its item order and single-launch flag."""
     a, b = tag_a.split(","), tag_b.split(",")
-    return a[:2] == b[:2] if kernel == "nstage" else a[2] == b[2]
+    a += ["0"] * (4 - len(a))
+    b += ["0"] * (4 - len(b))
+    return a[:2] == b[:2] if kernel == "nstage" else a[2:4] == b[2:4]
 
 
 def recorded_traffic(kernel, precision, workload, tuning):
@@ -401,6 +411,20 @@ def main():
         fp64 = {"ms_per_step": t64 * 1e3, "build_ms": b64, "build_tflops": a64 / (b64 * 1e-3) / 1e12,
                 "ec_time_ms": e64, "Ec_per_atom": ec64 / inp.natoms}
     plan, ws = make_plan(args.precision)
+    # tau points per launch: as many as keep the per-tau part of the workspace within the budget
+    ws1 = plan.workspace_bytes
+    tb = args.tau_batch
+    if tb <= 0:
+        tb = nt
+        while tb > 1:
+            need = plan.set_tau_batch(tb)
+            if need - ws1 <= args.tau_batch_gib * 2 ** 30:
+                break
+            tb = max(1, tb // 2)
+    need = plan.set_tau_batch(min(tb, nt))
+    del ws
+    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    log("tau points per launch: %d (workspace %.1f GB)" % (min(tb, nt), need / 1e9))
     alg_flops, exec_flops = plan.flops()
     if args.tuning == "auto":
         # times the variants on tau_0 (outside the timed steps); chi_tau[0] is the scratch
@@ -427,6 +451,34 @@ def main():
         build_chi0_tau(plan, inp.spin_factor, Gocc, Gun, C, ws, chi_tau)
         torch.cuda.synchronize()
         chi_err = float(torch.linalg.vector_norm(chi_tau - chi64) / torch.linalg.vector_norm(chi64))
+    if args.screening > 0:
+        # the Green's-function-screened build of the same plan (threshold of the paper's case
+        # study by default), outside the timed steps: one untimed and one timed build, the kept
+        # share of the fused kernel's K(R1) slices, and its chi and E_c against the FP64 path
+        plan.set_screening(args.screening)
+        build_chi0_tau(plan, inp.spin_factor, Gocc, Gun, C, ws, chi_tau)
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        build_chi0_tau(plan, inp.spin_factor, Gocc, Gun, C, ws, chi_tau)
+        sb_ms = sum(ctx.profile_read(k)[0] for k in ("pack_c", "pad_g", "screen", "nstage", "fused"))
+        sf_ms = ctx.profile_read("fused")[0]
+        ctx.profile(False)
+        st = plan.screening_stats()
+        rec_s = {"theta": args.screening, "build_ms": sb_ms, "fused_ms": sf_ms,
+                 "build_speedup_vs_unscreened": build_ms / sb_ms,
+                 "slices_kept_frac": st["slices_kept"] / max(st["slices_total"], 1),
+                 "z_kept_frac": st["z_kept"] / max(st["z_total"], 1)}
+        if chi64 is not None:
+            rec_s["chi_rel_err_vs_fp64"] = float(torch.linalg.vector_norm(chi_tau - chi64) /
+                                                 torch.linalg.vector_norm(chi64))
+            chi0_tau_to_omega(ctx, inp.gamma_cos, chi_tau, chi_w)
+            chi0_R_to_q(ctx, cell.mesh, inp.kfrac, chi_w, chi_q_view())
+            ec_s, _ = rpa_correlation_energy(ctx, inp.womega, chi_q_view(), vq, ws_ec)
+            rec_s["dEc_per_atom_vs_fp64"] = abs(ec_s - fp64["Ec_per_atom"] * inp.natoms) / inp.natoms
+        plan.set_screening(0.0)
+        extra["screened"] = rec_s
+        log("screened build: %s" % rec_s)
+    if chi64 is not None:
         del chi64
 
     # the Green's functions of the step's input, built on the GPU from the eigenpairs (outside the

@@ -58,9 +58,11 @@ typedef enum {
 typedef enum {
   RPA_FP64 = 0,             /* every contraction in FP64 (MFMA f64) */
   RPA_FP32 = 1,             /* contractions in FP32 (MFMA f32), FP64 across neighbour blocks */
-  RPA_BF16X3 = 2            /* N stage as RPA_FP32; the neighbour loop (O and chi += C O) in
-                               split BF16: x = hi + lo, a b = a_hi b_hi + a_hi b_lo + a_lo b_hi
-                               on the bf16 MFMAs, FP32 accumulation, FP64 across neighbour blocks */
+  RPA_BF16X3 = 2            /* the N stage and the neighbour loop (O and chi += C O) in split
+                               BF16: x = hi + lo, a b = a_hi b_hi + a_hi b_lo + a_lo b_hi on the
+                               bf16 MFMAs, FP32 accumulation, FP64 across neighbour blocks; the
+                               Z terms in FP32.  A plan whose split operands of the N stage
+                               exceed 4 GiB per part runs that stage as RPA_FP32 */
 } rpa_precision;
 
 typedef struct rpa_ctx rpa_ctx;
@@ -128,6 +130,14 @@ RPA_API int rpa_plan_stage_flops(const rpa_plan *plan, int stage, double *alg_fl
  *   from_cache   : 1 if rpa_plan_autotune took the choice from the context's cache
  *   nstage_ms, fused_ms : measured duration of one tau with the chosen variants
  *                  (0 when not measured)
+ *   fused_single : 0 one fused launch per template class (the atom classes of the
+ *                  uneven blocks: ABF tiles of U, NAO steps of V, NAO tiles of U) and tau;
+ *                  1 or 2 (split-BF16 plans only) one launch for every class and every tau
+ *                  of a chunk (rpa_plan_set_tau_batch), with the work of each tau in order of
+ *                  decreasing size so that the compute units that finish early take the
+ *                  small items; 1: workgroups of 8 waves, one per item (up to 128 ABF columns
+ *                  of V); 2: workgroups of 4 waves, one per half of an item's columns (an
+ *                  item with at most 64 columns takes one), two workgroups per compute unit
  * Every variant computes the same chi; the item order leaves it bitwise unchanged,
  * the K step changes the FP32/FP64 summation order only. */
 typedef struct {
@@ -137,6 +147,7 @@ typedef struct {
   int from_cache;
   double nstage_ms;
   double fused_ms;
+  int fused_single;
 } rpa_tuning;
 
 /* Autotuner: times every variant of the N-stage kernel, then of the fused kernel,
@@ -159,11 +170,47 @@ RPA_API int rpa_plan_get_tuning(const rpa_plan *plan, rpa_tuning *out);
  * the ranges above are rejected with RPA_ERR_ARG and leave the plan unchanged. */
 RPA_API int rpa_plan_set_tuning(rpa_plan *plan, const rpa_tuning *t);
 
+/* tau points per launch.  By default every tau runs its own N-stage and fused launches (the
+ * workspace holds padded G and the N intermediate of one tau).  rpa_plan_set_tau_batch sets
+ * ntau_per_launch in [1, ntau]: G of that many tau points is padded and screened in turn, then one
+ * N-stage launch and one fused launch (or one per template class and tau, see fused_single) cover
+ * them all, and the workspace holds their padded G and N side by side.  *workspace_bytes receives
+ * the new workspace size (for the N intermediate it grows with ntau_per_launch); every later
+ * compute call of the plan needs that much.  rpa_plan_workspace_bytes returns the current size.
+ * Errors: RPA_ERR_ARG, RPA_ERR_HIP. */
+RPA_API int rpa_plan_set_tau_batch(rpa_plan *plan, int ntau_per_launch, size_t *workspace_bytes);
+RPA_API int rpa_plan_workspace_bytes(const rpa_plan *plan, size_t *workspace_bytes);
+
+/* Green's-function screening of the chi0 build (the paper's lever for linear scaling: the
+ * decay of G limits the range of the lattice vector R on top of the locality of the LRI
+ * neighbourhoods, Sec. 2 after Algorithm 1; its case study screens on G with a threshold of
+ * 1e-3, Sec. 6).  The paper states no rule; this library bounds every term of Algorithm 1 by its
+ * two Green's-function factors.  Per tau, from the FP64 G input:
+ *   gb(U, V, R)  = max over s, i in U, j in V of |G^s_ij(R, tau)|
+ *   gn(V, K, dR) = max over L(dL) in N[V] of gb(L, K, dR - dL)   (bounds every G inside N(V, K, dR))
+ *   g            = max of gb,  cut = (theta g) g
+ * For the block chi_UV(R, tau), the M terms of neighbour K(R1) of U (G_UV(R) times N(V, K, R1 - R))
+ * are dropped when gb(U, V, R) gn(V, K, R1 - R) < cut, and the Z terms when
+ * gn(U, V, R) gn(V, U, -R) < cut (FP64 products; a block whose terms are all dropped is written as
+ * zero, which restricts the R range).  theta = 0 (the default) drops nothing and gives exactly the
+ * unscreened build; theta > 1 drops everything.  Every dropped term is bounded elementwise by
+ * 2 s gb gn times sums of |C|, so the error vanishes with theta.
+ * rpa_plan_set_screening sets theta (finite, >= 0; RPA_ERR_ARG otherwise) for the following
+ * builds of the plan, and on first use with theta > 0 allocates a small plan-owned device buffer
+ * (2 natoms^2 nR doubles of bounds and 3 ints per fused-kernel item and tau of statistics).
+ * rpa_plan_screening_stats waits for the context's stream and returns, for the last
+ * build_chi0_tau of the plan with screening on (RPA_ERR_ARG if there is none since theta was
+ * set), host out[6] = {neighbour entries kept, entries in total, K(R1) slices kept, slices in
+ * total, blocks whose Z terms were kept, blocks in total}, summed over all (U <= V, R, tau).
+ * Errors: RPA_ERR_ARG, RPA_ERR_HIP. */
+RPA_API int rpa_plan_set_screening(rpa_plan *plan, double theta);
+RPA_API int rpa_plan_screening_stats(rpa_plan *plan, long long *out);
+
 /* Opt-in kernel timing with HIP events recorded on the context's stream around
  * every launch of the library's kernels.  rpa_profile(ctx, 1) enables and resets,
  * rpa_profile(ctx, 0) disables.  rpa_profile_read waits for the recorded events and
  * returns the summed duration and launch count of one kernel ("pack_c", "pad_g",
- * "nstage", "fused", "cos_transform", "r2q", "ec_stage", "green").  Errors: RPA_ERR_ARG, RPA_ERR_HIP. */
+ * "screen", "nstage", "fused", "cos_transform", "r2q", "ec_stage", "green").  Errors: RPA_ERR_ARG, RPA_ERR_HIP. */
 RPA_API int rpa_profile(rpa_ctx *ctx, int enable);
 RPA_API int rpa_profile_read(rpa_ctx *ctx, const char *kernel, double *total_ms, int *launches);
 
@@ -198,6 +245,17 @@ RPA_API size_t rpa_green_workspace_size(int nk, int nb, int nocc);
 RPA_API int build_green_tau(rpa_ctx *ctx, int nk, int nb, int nocc, double mu, int ntau, const double *tau,
                             const int mesh[3], const double *k_frac, const double *eps, const double *wfc,
                             void *workspace, size_t workspace_bytes, double *G_occ, double *G_un);
+
+/* Check of the precondition of build_chi0_tau that the Green's functions are real and symmetric
+ * under R -> -R with transposition, G^s(-R) = G^s(R)^T (time reversal; the kernels take the X
+ * intermediate of Algorithm 1 as a transposed N block and rely on it):
+ *   G_occ, G_un : device FP64 [ntau][nR][nb][nb] on the BvK mesh `mesh`
+ *   *rel_dev    : host, receives max |G^s(-R)_ji - G^s(R)_ij| / max |G^s(R)_ij| (may be null)
+ * Returns RPA_ERR_ARG when the relative deviation exceeds tol (or is not a number); inputs that
+ * fail it give a chi that is not Algorithm 1's.  Synchronises the context's stream.
+ * Errors: RPA_ERR_ARG, RPA_ERR_HIP. */
+RPA_API int rpa_check_green_symmetry(rpa_ctx *ctx, int ntau, const int mesh[3], int nb, const double *G_occ,
+                                     const double *G_un, double tol, double *rel_dev);
 
 /* Cosine transform tau -> i omega (Sec. 2, the chi0(R, i omega_k) equation):
  *   chi(R, i omega_k) = sum_j Gamma_kj chi(R, tau_j),  Gamma_kj = gamma_jk cos(tau_j omega_k)
@@ -306,6 +364,72 @@ RPA_API int rpa_batch_result(rpa_batch *batch, double *Ec, double *Ec_q);
 /* Waits for the device, then frees the graph, the lane streams and the batch's
  * small device buffers.  The plans stay owned by the caller. */
 RPA_API int rpa_batch_destroy(rpa_batch *batch);
+
+/* ---- Input session shaped like the paper's library interface (App. B) -----------------
+ * For host programs (NAO DFT codes) that hand over their data the way the paper's interface
+ * takes it: dimensions, band energies and occupations, Bloch eigenvectors per k, lattice and k
+ * mesh, irreducible k points with weights, LRI coefficients per atom pair with a lattice vector,
+ * the Coulomb matrix per atom pair or per 2D block, then one call for the correlation energy.
+ * All arrays are HOST arrays owned by the caller and copied by the call; the session keeps its
+ * own host copies, and rpa_get_rpa_correlation_energy allocates and frees the device memory it
+ * needs.  Units: Hartree and Bohr (or any consistent pair).  Closed shells only.
+ * Readings of the listing: rpa_corr and rpa_corr_irk_contrib are real (E_c is real by
+ * construction); wfc_real / wfc_imag hold c_{i n}(k) band-major, [nstates][nbasis]; wg are
+ * occupation weights, and a band counts as occupied when |wg| exceeds half the largest |wg| (the
+ * occupied bands must come first and be as many at every k: an insulator); the minimax time and
+ * frequency grids, which the paper's library generates itself, are an input here
+ * (rpa_set_time_freq_grids).  Errors: RPA_ERR_ARG, RPA_ERR_SHAPE, RPA_ERR_UNSUPPORTED and those
+ * of the compute calls; rpa_session_last_error() describes the last one. */
+typedef struct rpa_session rpa_session;
+RPA_API int rpa_session_create(rpa_ctx *ctx, rpa_session **session);
+RPA_API int rpa_session_destroy(rpa_session *session);
+RPA_API const char *rpa_session_last_error(const rpa_session *session);
+/* Arithmetic of the chi0 build (rpa_precision; RPA_FP64 by default). */
+RPA_API int rpa_session_set_precision(rpa_session *session, int precision);
+/* nspins (must be 1), nkpts (= N1 N2 N3 of the k mesh), nstates (bands), nbasis (NAOs of the
+ * cell), natoms.  Resets the eigenvectors and bands. */
+RPA_API int rpa_set_dimension(rpa_session *session, int nspins, int nkpts, int nstates, int nbasis, int natoms);
+/* wg, ekb: [nspins][nkpts][nstates] occupation weights and band energies; efermi: the chemical
+ * potential mu of the Green's functions. */
+RPA_API int rpa_set_wg_ekb_efermi(rpa_session *session, int nspins, int nkpts, int nstates, const double *wg,
+                                  const double *ekb, double efermi);
+/* Eigenvectors at (ispin, ik): wfc_real, wfc_imag [nstates][nbasis], c_{i n}(k) at [n][i]. */
+RPA_API int rpa_set_ao_basis_wfc(rpa_session *session, int ispin, int ik, const double *wfc_real,
+                                 const double *wfc_imag);
+/* lat_mat: lattice vectors a_d as rows; G_mat: reciprocal vectors as rows (kept, not needed). */
+RPA_API int rpa_set_latvec_and_G(rpa_session *session, const double lat_mat[9], const double G_mat[9]);
+/* k mesh N1 x N2 x N3 (Gamma-centred BvK mesh) and the Cartesian k vectors [nkpts][3] in the
+ * mesh order (k index (n1 N2 + n2) N3 + n3); fractional coordinates are k . a_d / (2 pi). */
+RPA_API int rpa_set_kgrids_kvec_tot(rpa_session *session, int nk1, int nk2, int nk3, const double *kvecs);
+/* Irreducible k (= q) points: indices into the k list and weights (normalised to sum 1 by the
+ * library).  Without this call every k point is a q point of weight 1/nkpts.  Clears the Coulomb
+ * matrices set so far (their q index refers to this list). */
+RPA_API int rpa_set_ibz2bz_index_and_weight(rpa_session *session, int nk_irk, const int *ibz2bz_index,
+                                            const double *wk_irk);
+/* LRI block of atom I with atom J displaced by the integer lattice vector R[3]:
+ * Cs_in[mu][i][j] for mu on I (naux_mu), i on I (nbasis_i), j on J (nbasis_j), as rpa_lri_blocks;
+ * insert_index_only = 1 registers the block with zero coefficients.  A later call for the same
+ * (I, J, R) replaces the block.  Every atom needs its own block (I, I, 0) for its sizes. */
+RPA_API int rpa_set_ao_basis_aux(rpa_session *session, int I, int J, int nbasis_i, int nbasis_j, int naux_mu,
+                                 const int *R, const double *Cs_in, int insert_index_only);
+/* Coulomb matrix v(q) of q index ik (into the irreducible list, or the k list): the block of atoms
+ * (I, J), [naux_mu][naux_nu] real and imaginary parts (needs the LRI blocks for the ABF offsets),
+ * or the block [mu_begin, mu_end) x [nu_begin, nu_end) of the max_naux x max_naux matrix.  Every
+ * element of every q must be set before the energy call. */
+RPA_API int rpa_set_aux_bare_coulomb_k_atom_pair(rpa_session *session, int ik, int I, int J, int naux_mu,
+                                                 int naux_nu, const double *Vq_real_in, const double *Vq_imag_in);
+RPA_API int rpa_set_aux_bare_coulomb_k_2D_block(rpa_session *session, int ik, int max_naux, int mu_begin,
+                                                int mu_end, int nu_begin, int nu_end, const double *Vq_real_in,
+                                                const double *Vq_imag_in);
+/* Minimax grids: tau[ngrid], frequency weights[ngrid] and the cosine-transform weights
+ * gamma_cos[ngrid][ngrid] (as chi0_tau_to_omega) with as many frequencies as time points. */
+RPA_API int rpa_set_time_freq_grids(rpa_session *session, int ngrid, const double *tau, const double *omega_weights,
+                                    const double *gamma_cos);
+/* Runs build_green_tau, build_chi0_tau, chi0_tau_to_omega, chi0_R_to_q and rpa_correlation_energy on
+ * the session's data (the q points of the irreducible list) and returns *rpa_corr = E_c per cell
+ * and, if rpa_corr_irk_contrib is not null, the contribution of every irreducible q point,
+ * w_q (1/2 pi) sum_k w_k {ln det[1 - chi0 v] + Tr[chi0 v]} ([nk_irk], summing to E_c). */
+RPA_API int rpa_get_rpa_correlation_energy(rpa_session *session, double *rpa_corr, double *rpa_corr_irk_contrib);
 
 #ifdef __cplusplus
 }

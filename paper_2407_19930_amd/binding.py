@@ -26,7 +26,13 @@ EXPORTED = ["rpa_create", "rpa_set_stream", "rpa_destroy", "rpa_last_error", "rp
             "rpa_correlation_energy", "rpa_batch_create", "rpa_batch_run", "rpa_batch_result",
             "rpa_batch_destroy", "rpa_plan_autotune", "rpa_plan_get_tuning", "rpa_plan_set_tuning",
             "rpa_green_workspace_size", "build_green_tau", "rpa_noalloc_scratch_bytes",
-            "rpa_correlation_energy_noalloc"]
+            "rpa_correlation_energy_noalloc", "rpa_plan_set_screening", "rpa_plan_screening_stats",
+            "rpa_plan_set_tau_batch", "rpa_plan_workspace_bytes", "rpa_session_create", "rpa_session_destroy",
+            "rpa_session_last_error", "rpa_session_set_precision", "rpa_set_dimension", "rpa_set_wg_ekb_efermi",
+            "rpa_set_ao_basis_wfc", "rpa_set_latvec_and_G", "rpa_set_kgrids_kvec_tot",
+            "rpa_set_ibz2bz_index_and_weight", "rpa_set_ao_basis_aux", "rpa_set_aux_bare_coulomb_k_atom_pair",
+            "rpa_set_aux_bare_coulomb_k_2D_block", "rpa_set_time_freq_grids", "rpa_get_rpa_correlation_energy",
+            "rpa_check_green_symmetry"]
 
 
 class RpaError(RuntimeError):
@@ -58,7 +64,8 @@ class _BatchCell(ctypes.Structure):
 class Tuning(ctypes.Structure):
     """rpa_tuning: launch variants of a plan's N-stage and fused kernels."""
     _fields_ = [("nstage_order", ctypes.c_int), ("nstage_kstep", ctypes.c_int), ("fused_order", ctypes.c_int),
-                ("from_cache", ctypes.c_int), ("nstage_ms", ctypes.c_double), ("fused_ms", ctypes.c_double)]
+                ("from_cache", ctypes.c_int), ("nstage_ms", ctypes.c_double), ("fused_ms", ctypes.c_double),
+                ("fused_single", ctypes.c_int)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -109,9 +116,30 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.rpa_plan_autotune.argtypes = [vp, dp, vp, vp, vp, vp, sz, vp, ctypes.POINTER(Tuning)]
     lib.rpa_plan_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
     lib.rpa_plan_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
+    lib.rpa_plan_set_screening.argtypes = [vp, dp]
+    lib.rpa_plan_set_tau_batch.argtypes = [vp, i, ctypes.POINTER(sz)]
+    lib.rpa_plan_workspace_bytes.argtypes = [vp, ctypes.POINTER(sz)]
+    lib.rpa_plan_screening_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong)]
+    lib.rpa_check_green_symmetry.argtypes = [vp, i, ctypes.POINTER(ctypes.c_int), i, vp, vp, dp, ctypes.POINTER(dp)]
+    lib.rpa_session_create.argtypes = [vp, ctypes.POINTER(vp)]
+    lib.rpa_session_destroy.argtypes = [vp]
+    lib.rpa_session_last_error.argtypes = [vp]
+    lib.rpa_session_last_error.restype = ctypes.c_char_p
+    lib.rpa_session_set_precision.argtypes = [vp, i]
+    lib.rpa_set_dimension.argtypes = [vp, i, i, i, i, i]
+    lib.rpa_set_wg_ekb_efermi.argtypes = [vp, i, i, i, vp, vp, dp]
+    lib.rpa_set_ao_basis_wfc.argtypes = [vp, i, i, vp, vp]
+    lib.rpa_set_latvec_and_G.argtypes = [vp, vp, vp]
+    lib.rpa_set_kgrids_kvec_tot.argtypes = [vp, i, i, i, vp]
+    lib.rpa_set_ibz2bz_index_and_weight.argtypes = [vp, i, vp, vp]
+    lib.rpa_set_ao_basis_aux.argtypes = [vp, i, i, i, i, i, vp, vp, i]
+    lib.rpa_set_aux_bare_coulomb_k_atom_pair.argtypes = [vp, i, i, i, i, i, vp, vp]
+    lib.rpa_set_aux_bare_coulomb_k_2D_block.argtypes = [vp, i, i, i, i, i, i, vp, vp]
+    lib.rpa_set_time_freq_grids.argtypes = [vp, i, vp, vp, vp]
+    lib.rpa_get_rpa_correlation_energy.argtypes = [vp, ctypes.POINTER(dp), vp]
     for name in EXPORTED:
         if name not in ("rpa_destroy", "rpa_last_error", "rpa_ec_workspace_size", "rpa_green_workspace_size",
-                        "rpa_noalloc_scratch_bytes"):
+                        "rpa_noalloc_scratch_bytes", "rpa_session_last_error"):
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -244,9 +272,27 @@ class Plan:
         self.ctx.check(self.ctx.lib.rpa_plan_get_tuning(self.h, ctypes.byref(t)))
         return t
 
-    def set_tuning(self, nstage_order: int, nstage_kstep: int, fused_order: int):
-        t = Tuning(int(nstage_order), int(nstage_kstep), int(fused_order), 0, 0.0, 0.0)
+    def set_tuning(self, nstage_order: int, nstage_kstep: int, fused_order: int, fused_single: int = 0):
+        t = Tuning(int(nstage_order), int(nstage_kstep), int(fused_order), 0, 0.0, 0.0, int(fused_single))
         self.ctx.check(self.ctx.lib.rpa_plan_set_tuning(self.h, ctypes.byref(t)))
+
+    def set_tau_batch(self, ntau_per_launch: int) -> int:
+        """rpa_plan_set_tau_batch: tau points per launch; returns (and keeps) the new workspace size."""
+        ws = ctypes.c_size_t()
+        self.ctx.check(self.ctx.lib.rpa_plan_set_tau_batch(self.h, int(ntau_per_launch), ctypes.byref(ws)))
+        self.workspace_bytes = ws.value
+        return ws.value
+
+    def set_screening(self, theta: float):
+        """rpa_plan_set_screening: Green's-function screening threshold (0 = off)."""
+        self.ctx.check(self.ctx.lib.rpa_plan_set_screening(self.h, float(theta)))
+
+    def screening_stats(self) -> dict:
+        """rpa_plan_screening_stats of the last screened build."""
+        out = (ctypes.c_longlong * 6)()
+        self.ctx.check(self.ctx.lib.rpa_plan_screening_stats(self.h, out))
+        keys = ("entries_kept", "entries_total", "slices_kept", "slices_total", "z_kept", "z_total")
+        return {k: int(v) for k, v in zip(keys, out)}
 
     def close(self):
         if getattr(self, "h", None) and getattr(self.ctx, "h", None):
@@ -297,6 +343,21 @@ def chi0_R_to_q(ctx: Context, mesh, q_frac, chi0_R, chi0_q):
         raise ValueError("output shape mismatch")
     mesh_a = (ctypes.c_int * 3)(*[int(x) for x in mesh])
     ctx.check(ctx.lib.chi0_R_to_q(ctx.h, mesh_a, nbatch, m, nq, qp, _dev(chi0_R, torch.float64), _dev(out)))
+
+
+def rpa_check_green_symmetry(ctx: Context, mesh, G_occ, G_un, tol: float = 1e-12) -> float:
+    """rpa_check_green_symmetry on device tensors [ntau, nR, nb, nb]; returns the relative deviation
+    (raises RpaError with RPA_ERR_ARG when it exceeds tol)."""
+    import torch
+    f64 = torch.float64
+    ntau, nR, nb = int(G_occ.shape[0]), int(G_occ.shape[1]), int(G_occ.shape[2])
+    if tuple(G_un.shape) != tuple(G_occ.shape) or nR != int(np.prod(mesh)) or int(G_occ.shape[3]) != nb:
+        raise ValueError("G_occ / G_un must both be [ntau, nR, nb, nb] on the mesh")
+    m = (ctypes.c_int * 3)(*[int(x) for x in mesh])
+    dev = ctypes.c_double()
+    ctx.check(ctx.lib.rpa_check_green_symmetry(ctx.h, ntau, m, nb, _dev(G_occ, f64), _dev(G_un, f64), float(tol),
+                                               ctypes.byref(dev)))
+    return dev.value
 
 
 def rpa_green_workspace_size(nk: int, nb: int, nocc: int) -> int:
@@ -416,6 +477,101 @@ class Batch:
     def close(self):
         if getattr(self, "h", None) and getattr(self.ctx, "h", None):
             self.ctx.lib.rpa_batch_destroy(self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Session:
+    """Input session shaped like the paper's library interface (rpa_session_* and rpa_set_* of the
+    C ABI).  Host numpy arrays in, E_c and the per-irreducible-q contributions out; the method
+    names are the C names without the rpa_ prefix."""
+
+    def __init__(self, ctx: Context):
+        self.ctx = ctx
+        h = ctypes.c_void_p()
+        ctx.check(ctx.lib.rpa_session_create(ctx.h, ctypes.byref(h)))
+        self.h = h
+        self.nq = None
+        ctx._plans.add(self)
+
+    def _check(self, rc):
+        if rc != 0:
+            raise RpaError(rc, self.ctx.lib.rpa_session_last_error(self.h).decode())
+
+    def set_precision(self, precision: str):
+        self._check(self.ctx.lib.rpa_session_set_precision(self.h, PRECISIONS[precision]))
+
+    def set_dimension(self, nspins, nkpts, nstates, nbasis, natoms):
+        self._check(self.ctx.lib.rpa_set_dimension(self.h, int(nspins), int(nkpts), int(nstates), int(nbasis),
+                                                   int(natoms)))
+        self.nq = int(nkpts)
+
+    def set_wg_ekb_efermi(self, nspins, nkpts, nstates, wg, ekb, efermi):
+        w, wp = _host(wg, np.float64)
+        e, ep = _host(ekb, np.float64)
+        self._check(self.ctx.lib.rpa_set_wg_ekb_efermi(self.h, int(nspins), int(nkpts), int(nstates), wp, ep,
+                                                       float(efermi)))
+
+    def set_ao_basis_wfc(self, ispin, ik, wfc_real, wfc_imag):
+        r, rp = _host(wfc_real, np.float64)
+        m, mp = _host(wfc_imag, np.float64)
+        self._check(self.ctx.lib.rpa_set_ao_basis_wfc(self.h, int(ispin), int(ik), rp, mp))
+
+    def set_latvec_and_G(self, lat_mat, G_mat):
+        a, ap = _host(lat_mat, np.float64)
+        g, gp = _host(G_mat, np.float64)
+        self._check(self.ctx.lib.rpa_set_latvec_and_G(self.h, ap, gp))
+
+    def set_kgrids_kvec_tot(self, nk1, nk2, nk3, kvecs):
+        k, kp = _host(kvecs, np.float64)
+        self._check(self.ctx.lib.rpa_set_kgrids_kvec_tot(self.h, int(nk1), int(nk2), int(nk3), kp))
+
+    def set_ibz2bz_index_and_weight(self, ibz2bz_index, wk_irk):
+        i, ip = _host(ibz2bz_index, np.int32)
+        w, wp = _host(wk_irk, np.float64)
+        self._check(self.ctx.lib.rpa_set_ibz2bz_index_and_weight(self.h, len(i), ip, wp))
+        self.nq = len(i)
+
+    def set_ao_basis_aux(self, I, J, nbasis_i, nbasis_j, naux_mu, R, Cs, insert_index_only=0):
+        r, rp = _host(R, np.int32)
+        c, cp = _host(Cs, np.float64) if Cs is not None else (None, None)
+        self._check(self.ctx.lib.rpa_set_ao_basis_aux(self.h, int(I), int(J), int(nbasis_i), int(nbasis_j),
+                                                      int(naux_mu), rp, cp, int(insert_index_only)))
+
+    def set_aux_bare_coulomb_k_atom_pair(self, ik, I, J, naux_mu, naux_nu, Vq_real, Vq_imag):
+        r, rp = _host(Vq_real, np.float64)
+        m, mp = _host(Vq_imag, np.float64)
+        self._check(self.ctx.lib.rpa_set_aux_bare_coulomb_k_atom_pair(self.h, int(ik), int(I), int(J), int(naux_mu),
+                                                                      int(naux_nu), rp, mp))
+
+    def set_aux_bare_coulomb_k_2D_block(self, ik, max_naux, mu_begin, mu_end, nu_begin, nu_end, Vq_real, Vq_imag):
+        r, rp = _host(Vq_real, np.float64)
+        m, mp = _host(Vq_imag, np.float64)
+        self._check(self.ctx.lib.rpa_set_aux_bare_coulomb_k_2D_block(self.h, int(ik), int(max_naux), int(mu_begin),
+                                                                     int(mu_end), int(nu_begin), int(nu_end), rp, mp))
+
+    def set_time_freq_grids(self, tau, omega_weights, gamma_cos):
+        t, tp = _host(tau, np.float64)
+        w, wp = _host(omega_weights, np.float64)
+        g, gp = _host(gamma_cos, np.float64)
+        self._check(self.ctx.lib.rpa_set_time_freq_grids(self.h, len(t), tp, wp, gp))
+
+    def get_rpa_correlation_energy(self):
+        """(E_c per cell, contributions of the irreducible q points)."""
+        ec = ctypes.c_double()
+        contrib = np.zeros(self.nq or 0)
+        self._check(self.ctx.lib.rpa_get_rpa_correlation_energy(self.h, ctypes.byref(ec),
+                                                                contrib.ctypes.data_as(ctypes.c_void_p)))
+        return ec.value, contrib
+
+    def close(self):
+        if getattr(self, "h", None) and getattr(self.ctx, "h", None):
+            self.ctx.lib.rpa_session_destroy(self.h)
         self.h = None
 
     def __del__(self):

@@ -10,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "librpa_mi355x.so")
 SOURCES = ["api.hip", "chi0_kernels.hip", "chi0_bf16.hip", "transform_kernels.hip", "ec_kernels.hip",
-           "green_kernels.hip"]
+           "green_kernels.hip", "screen_kernels.hip",
+           "session.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-fvisibility=hidden",
          # no packed FP32 instructions (v_pk_*_f32) anywhere in the device code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

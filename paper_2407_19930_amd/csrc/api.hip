@@ -147,7 +147,7 @@ struct rpa_plan {
   // XCD-grouped orders of the same tiles and items (items permuted within each group)
   NTiles tiles_x{};
   PairItems items_x{};
-  rpa_tuning tune{0, 16, 0, 0, 0.0, 0.0};
+  rpa_tuning tune{0, 16, 0, 0, 0.0, 0.0, 0};
   std::string shape_key;                        // autotuner cache key (without the architecture)
   // split-BF16 N stage (BF16X3 plans whose hi and lo parts of transposed G and C each fit a
   // 32-bit buffer view; other BF16X3 plans run the FP32 N stage)
@@ -160,8 +160,22 @@ struct rpa_plan {
   std::vector<int4> ngrp;
   std::vector<long long> ngrp_off;
   unsigned gt_bytes = 0, ct_bytes = 0;          // one part (hi or lo)
-  // workspace layout (bytes)
+  // workspace layout (bytes); the per-tau parts (padded G, N, transposed G, G-scale exponents)
+  // are held for `slots` tau points at once, g_slot, n_slot, gt_slot bytes apart
   size_t ws_cp = 0, ws_cb = 0, ws_g = 0, ws_n = 0, ws_sc = 0, ws_gt = 0, ws_ct = 0, ws_total = 0;
+  size_t g_slot = 0, n_slot = 0, gt_slot = 0;
+  int slots = 1;                                // tau points per N-stage / fused launch
+  // single fused launch of the split-BF16 path: per plan item its class code and the items in
+  // order of decreasing work
+  std::vector<int> item_cls, item_order, half_order;   // half_order: 2 item + half (4-wave units)
+  const int *d_item_cls = nullptr, *d_item_order = nullptr, *d_half_order = nullptr;
+  // Green's-function screening (off while theta == 0): a plan-owned device buffer with the
+  // bounds of one tau (gb, gn, gc) and the per-item statistics of every tau of the last build
+  double theta = 0.0;
+  void *dscr = nullptr;
+  double *scr_gb = nullptr, *scr_gn = nullptr, *scr_gc = nullptr;
+  int *scr_stats = nullptr;                     // [ntau][items][3]
+  bool scr_valid = false;                       // statistics of a complete build are present
 
   PairItems group_items(const PlanGroup &g, int order = 0) const {
     const PairItems &it = order ? items_x : items;
@@ -173,7 +187,7 @@ struct rpa_plan {
 // ---- correlation energy ----
 namespace {
 struct EcLayout {
-  size_t L, T, B, W, trB, f, flags, ecq, w, total;
+  size_t L, T, B, W, trB, f, flags, ecq, w, realq, total;
   int cw;
 };
 // L: Cholesky factors of v(q) for every q; T, B: cw (q, omega) matrices at a time
@@ -199,6 +213,8 @@ EcLayout ec_layout(int n, int nq, int nomega, int cw) {
   o = align_up(o + (size_t)(nq + 1) * 8);
   l.w = o;
   o = align_up(o + (size_t)nomega * 8);
+  l.realq = o;
+  o = align_up(o + (size_t)nq * 4);
   l.total = o;
   l.cw = cw;
   return l;
@@ -230,9 +246,12 @@ bool ec_fit_layout(int n, int nq, int nomega, size_t workspace_bytes, EcLayout &
 // Status flags written by the energy stage: [nq] for the Cholesky of v(q), then
 // [nq][nomega] for 1 - L^H chi L (1: not positive definite, 2: non-finite log-determinant).
 int ec_check_flags(rpa_ctx *ctx, const int *hflags, int nq, int nomega, const std::string &where) {
-  for (int q = 0; q < nq; ++q)
+  for (int q = 0; q < nq; ++q) {
+    if (hflags[q] == 2)
+      return fail(ctx, RPA_ERR_NONFINITE, where + "NaN or Inf in v(q) at q index " + std::to_string(q));
     if (hflags[q])
       return fail(ctx, RPA_ERR_NOT_HPD, where + "v(q) is not Hermitian positive definite at q index " + std::to_string(q));
+  }
   for (int q = 0; q < nq; ++q)
     for (int k = 0; k < nomega; ++k) {
       const int fl = hflags[nq + q * nomega + k];
@@ -255,9 +274,12 @@ int ec_enqueue(rpa_ctx *ctx, hipStream_t s, int n, int nq, int nomega, const dou
   double *L = (double *)(ws + l.L), *T = (double *)(ws + l.T), *B = (double *)(ws + l.B),
          *W = (double *)(ws + l.W), *trB = (double *)(ws + l.trB), *f = (double *)(ws + l.f),
          *ecq = (double *)(ws + l.ecq);
-  int *flags = (int *)(ws + l.flags);
+  int *flags = (int *)(ws + l.flags), *realq = (int *)(ws + l.realq);
   const size_t mat = (size_t)n * n * 2;   // doubles per complex matrix
   HIP_TRY(ctx, launch_fill_int(flags, (size_t)(nq + nq * nomega), 0, s));
+  // q points whose chi(q, i omega) is real at every omega (time-reversal invariant q, where the
+  // phases of R -> q are +1 or -1): T = chi L there takes two real products per complex one
+  HIP_TRY(ctx, launch_real_flags(chi0_q, n, nq, nomega, realq, s));
   // v(q) = L_q L_q^H for every q at once
   HIP_TRY(ctx, launch_copy_words(L, v_q, nq * mat * 2, s));
   HIP_TRY(ctx, launch_cholesky(L, mat, n, nq, W, flags, 0, s));
@@ -284,6 +306,7 @@ int ec_enqueue(rpa_ctx *ctx, hipStream_t s, int n, int nq, int nomega, const dou
     g.binner = nomega;
     g.alpha = 1.0;
     g.kmode = 1;
+    g.realA = realq;
     HIP_TRY(ctx, launch_zgemm(g, nb, s));
     // B = L_q^H T, lower triangle (L^H upper triangular: k >= first row of the tile)
     ZgemmArgs h{};
@@ -322,8 +345,16 @@ std::vector<double> r2q_phases(const int mesh[3], int nq, const double *q_frac) 
       const int n0 = r / (mesh[1] * mesh[2]), n1 = (r / mesh[2]) % mesh[1], n2 = r % mesh[2];
       double x = q_frac[3 * q] * n0 + q_frac[3 * q + 1] * n1 + q_frac[3 * q + 2] * n2;
       x -= std::floor(x);
-      ph[((size_t)q * nR + r) * 2] = std::cos(2.0 * M_PI * x);
-      ph[((size_t)q * nR + r) * 2 + 1] = std::sin(2.0 * M_PI * x);
+      double c = std::cos(2.0 * M_PI * x), sn = std::sin(2.0 * M_PI * x);
+      // quarter turns exactly (sin(pi) is not zero in floating point): chi(q) of a
+      // time-reversal invariant q then comes out exactly real
+      if (x == 0.0 || x == 0.25 || x == 0.5 || x == 0.75) {
+        const int k = (int)(4.0 * x);
+        c = k == 0 ? 1.0 : (k == 2 ? -1.0 : 0.0);
+        sn = k == 1 ? 1.0 : (k == 3 ? -1.0 : 0.0);
+      }
+      ph[((size_t)q * nR + r) * 2] = c;
+      ph[((size_t)q * nR + r) * 2 + 1] = sn;
     }
   return ph;
 }
@@ -383,6 +414,10 @@ struct BuildSteps {
     Cth = (uint16_t *)(ws + p->ws_ct);
     Ctl = (uint16_t *)(ws + p->ws_ct + align_up(p->ct_bytes));
   }
+  // per-slot views
+  T *gp_at(int k) const { return (T *)((char *)Gp + k * p->g_slot); }
+  T *n_at(int k) const { return (T *)((char *)Nb + k * p->n_slot); }
+  int *gexp_at(int k) const { return gexp ? gexp + 2 * k : nullptr; }
   int pack(const double *C) {
     Timed tm(ctx, "pack_c");
     if (nbf)
@@ -392,34 +427,93 @@ struct BuildSteps {
     if (bf16) HIP_TRY(ctx, launch_pack_cb(p->pack, C, Cb, p->maxblk * 4, s));
     return RPA_OK;
   }
-  int pad(const double *G_occ, const double *G_un, int t) {
+  // G of tau t into slot k
+  int pad(const double *G_occ, const double *G_un, int t, int k = 0) {
     Timed tm(ctx, "pad_g");
-    if (gexp) HIP_TRY(ctx, launch_gscale(G_occ + t * gstride, G_un + t * gstride, gstride, gpart, gexp, s));
-    HIP_TRY(ctx, launch_pad_g<T>(G_occ + t * gstride, G_un + t * gstride, p->nR, p->nb, p->nbp, gexp, Gp, s));
+    int *ge = gexp_at(k);
+    if (ge) HIP_TRY(ctx, launch_gscale(G_occ + t * gstride, G_un + t * gstride, gstride, gpart, ge, s));
+    HIP_TRY(ctx, launch_pad_g<T>(G_occ + t * gstride, G_un + t * gstride, p->nR, p->nb, p->nbp, ge, gp_at(k), s));
     if (nbf)
       HIP_TRY(ctx, launch_pad_gt(G_occ + t * gstride, G_un + t * gstride, p->nR, p->nb, p->nbp, p->nbq, p->dgsrc,
-                                 gexp, GTh, GTl, s));
+                                 ge, (uint16_t *)((char *)GTh + k * p->gt_slot),
+                                 (uint16_t *)((char *)GTl + k * p->gt_slot), s));
     return RPA_OK;
   }
-  int nstage(const rpa_tuning &tu) {
+  // N of the first `ns` slots (one launch on the split-BF16 path, one per slot otherwise)
+  int nstage(const rpa_tuning &tu, int ns = 1) {
     Timed tm(ctx, "nstage");
     const NTiles &tiles = p->ntiles(tu.nstage_order);
     if (nbf)
-      HIP_TRY(ctx, launch_nstage_bf16(p->tb, tiles, GTh, GTl, p->gt_bytes, Cth, Ctl, p->ct_bytes, (float *)Nb, s));
+      HIP_TRY(ctx, launch_nstage_bf16(p->tb, tiles, GTh, GTl, p->gt_bytes, Cth, Ctl, p->ct_bytes, (float *)Nb, ns,
+                                      p->gt_slot / sizeof(uint16_t), p->n_slot / sizeof(float), s));
     else
-      HIP_TRY(ctx, launch_nstage<T>(p->tb, tiles, Gp, Cp, Nb, (size_t)p->cp_elems, tu.nstage_kstep, s));
+      for (int k = 0; k < ns; ++k)
+        HIP_TRY(ctx, launch_nstage<T>(p->tb, tiles, gp_at(k), Cp, n_at(k), (size_t)p->cp_elems, tu.nstage_kstep, s));
     return RPA_OK;
   }
-  int fused(const rpa_tuning &tu, double negs, double *chi_t) {
+  // Screening bounds of tau t (when the plan screens).
+  int screen(const double *G_occ, const double *G_un, int t, int k = 0) {
+    if (p->theta <= 0.0) return RPA_OK;
+    Timed tm(ctx, "screen");
+    const size_t nb3 = (size_t)p->natoms * p->natoms * p->nR;
+    HIP_TRY(ctx, launch_screen_norms(p->tb, G_occ + t * gstride, G_un + t * gstride, p->theta, p->scr_gb + k * nb3,
+                                     p->scr_gn + k * nb3, p->scr_gc + 2 * k, s));
+    return RPA_OK;
+  }
+  // chi of the first `ns` slots, slot k -> chi_t + k chistride.  stats_tau: tau of slot 0 for
+  // the per-item screening statistics, or -1 for none.  The split-BF16 path runs either one
+  // launch per template class and slot or, with tu.fused_single, one launch over every class
+  // and slot (items in order of decreasing work).
+  int fused(const rpa_tuning &tu, double negs, double *chi_t, int stats_tau = -1, int ns = 1) {
     Timed tm(ctx, "fused");
-    for (const PlanGroup &g : p->groups) {
-      if (bf16)
-        HIP_TRY(ctx, launch_fused_bf16(p->tb, p->group_items(g, tu.fused_order), g.mt, fused_bf16_ks_class(g.js), g.hc,
-                                       (const float *)Gp, Cb, (const float *)Nb, negs, gexp, chi_t, s));
-      else
-        HIP_TRY(ctx, launch_fused<T>(p->tb, p->group_items(g, tu.fused_order), g.mt, g.js, g.hc, Gp, Cp, Nb, negs,
-                                     gexp, chi_t, s));
+    const size_t nitems = p->itemU.size();
+    const size_t nb3 = (size_t)p->natoms * p->natoms * p->nR;
+    if (bf16 && tu.fused_single) {
+      SingleLaunch a{};
+      a.U = p->items.U;
+      a.V = p->items.V;
+      a.R = p->items.R;
+      a.cls = p->d_item_cls;
+      const bool halves = tu.fused_single == 2;
+      a.order = halves ? p->d_half_order : p->d_item_order;
+      a.nitems = halves ? (int)p->half_order.size() : (int)nitems;
+      a.nslots = ns;
+      a.Gp = (const float *)Gp;
+      a.gp_stride = p->g_slot / sizeof(float);
+      a.Cb = Cb;
+      a.Nbuf = (const float *)Nb;
+      a.n_stride = p->n_slot / sizeof(float);
+      a.gexp = gexp;
+      a.negs = negs;
+      a.chi = chi_t;
+      a.chi_stride = chistride;
+      if (p->theta > 0.0) {
+        a.gb = p->scr_gb;
+        a.gn = p->scr_gn;
+        a.gc = p->scr_gc;
+        if (stats_tau >= 0) {
+          a.stats = p->scr_stats + (size_t)stats_tau * nitems * 3;
+          a.stats_stride = nitems * 3;
+        }
+      }
+      HIP_TRY(ctx, launch_fused_bf16_single(p->tb, a, halves ? 4 : 8, s));
+      return RPA_OK;
     }
+    for (int k = 0; k < ns; ++k)
+      for (const PlanGroup &g : p->groups) {
+        Screen sc{nullptr, nullptr, nullptr, nullptr};
+        if (p->theta > 0.0) {
+          sc = Screen{p->scr_gb + k * nb3, p->scr_gn + k * nb3, p->scr_gc + 2 * k, nullptr};
+          if (stats_tau >= 0) sc.stats = p->scr_stats + ((size_t)(stats_tau + k) * nitems + g.start) * 3;
+        }
+        if (bf16)
+          HIP_TRY(ctx, launch_fused_bf16(p->tb, p->group_items(g, tu.fused_order), g.mt, fused_bf16_ks_class(g.js),
+                                         g.hc, (const float *)gp_at(k), Cb, (const float *)n_at(k), negs, gexp_at(k), sc,
+                                         chi_t + k * chistride, s));
+        else
+          HIP_TRY(ctx, launch_fused<T>(p->tb, p->group_items(g, tu.fused_order), g.mt, g.js, g.hc, gp_at(k), Cp,
+                                       n_at(k), negs, gexp_at(k), sc, chi_t + k * chistride, s));
+      }
     return RPA_OK;
   }
 };
@@ -429,11 +523,18 @@ static int build_impl(rpa_plan *p, const double *G_occ, const double *G_un, cons
                       double *chi0_tau, bool bf16) {
   BuildSteps<T> b(p, ws, bf16);
   int rc = b.pack(C);
-  for (int t = 0; rc == RPA_OK && t < p->ntau; ++t) {
-    rc = b.pad(G_occ, G_un, t);
-    if (rc == RPA_OK) rc = b.nstage(p->tune);
-    if (rc == RPA_OK) rc = b.fused(p->tune, negs, chi0_tau + t * b.chistride);
+  // tau points in chunks of p->slots: G of every tau of the chunk, then one N stage and the
+  // fused kernel over the chunk
+  for (int t0 = 0; rc == RPA_OK && t0 < p->ntau; t0 += p->slots) {
+    const int ns = std::min(p->slots, p->ntau - t0);
+    for (int k = 0; rc == RPA_OK && k < ns; ++k) {
+      rc = b.pad(G_occ, G_un, t0 + k, k);
+      if (rc == RPA_OK) rc = b.screen(G_occ, G_un, t0 + k, k);
+    }
+    if (rc == RPA_OK) rc = b.nstage(p->tune, ns);
+    if (rc == RPA_OK) rc = b.fused(p->tune, negs, chi0_tau + t0 * b.chistride, t0, ns);
   }
+  p->scr_valid = rc == RPA_OK && p->theta > 0.0;
   return rc;
 }
 
@@ -448,6 +549,7 @@ static int autotune_impl(rpa_plan *p, const double *G_occ, const double *G_un, c
   BuildSteps<T> b(p, ws, bf16);
   int rc = b.pack(C);
   if (rc == RPA_OK) rc = b.pad(G_occ, G_un, 0);
+  if (rc == RPA_OK) rc = b.screen(G_occ, G_un, 0);
   if (rc != RPA_OK) return rc;
   hipEvent_t e0, e1;
   HIP_TRY(ctx, hipEventCreate(&e0));
@@ -489,22 +591,46 @@ static int autotune_impl(rpa_plan *p, const double *G_occ, const double *G_un, c
     }
   // fused kernel on the N of the chosen N stage
   if (rc == RPA_OK) rc = b.nstage(best);
+  // fused kernel: item order of the per-class launches, then (split BF16) the single launch
   have = false;
-  for (int order = 0; rc == RPA_OK && order < 2; ++order) {
+  for (int cand = 0; rc == RPA_OK && cand < (bf16 ? 4 : 2); ++cand) {
     rpa_tuning c = best;
-    c.fused_order = order;
+    c.fused_order = cand == 1 ? 1 : 0;
+    c.fused_single = cand >= 2 ? cand - 1 : 0;
     float ms = 0.f;
     rc = timed([&]() { return b.fused(c, negs, chi_scratch); }, ms);
     if (rc == RPA_OK && (!have || ms < (1.f - kTuneMargin) * tbest)) {
       tbest = ms;
       have = true;
-      best.fused_order = order;
+      best.fused_order = c.fused_order;
+      best.fused_single = c.fused_single;
       best.fused_ms = ms;
     }
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   return rc;
+}
+
+// Workspace layout of a plan for p->slots tau points per launch: packed C (FP32 / FP64 N stage),
+// split-BF16 C (BF16X3 fused kernel), then per slot padded G and N, the G scale (partial maxima,
+// two exponents per slot), and for the split-BF16
+// N stage transposed G per slot (hi and lo parts) and C (hi and lo).
+static void plan_layout(rpa_plan *p) {
+  const size_t es = p->prec == RPA_FP64 ? 8 : 4;
+  const int ns = p->slots;
+  const size_t gtb = p->gt_bytes, ctb = p->ct_bytes;
+  p->ws_cp = 0;
+  p->ws_cb = align_up(p->nbf16 ? 0 : p->cp_elems * es);
+  p->ws_g = align_up(p->ws_cb + (p->prec == RPA_BF16X3 ? (size_t)p->cb_elems * 2 : 0));
+  p->g_slot = align_up(2 * (size_t)p->nR * p->nbp * p->nbp * es);
+  p->ws_n = align_up(p->ws_g + ns * p->g_slot);
+  p->n_slot = align_up((size_t)p->n_elems * es);
+  p->ws_sc = align_up(p->ws_n + ns * p->n_slot);
+  p->ws_gt = align_up(p->ws_sc + 2 * kGscaleBlocks * sizeof(double) + 2 * ns * sizeof(int));
+  p->gt_slot = p->nbf16 ? 2 * align_up(gtb) : 0;
+  p->ws_ct = align_up(p->ws_gt + ns * p->gt_slot);
+  p->ws_total = align_up(p->ws_ct + (p->nbf16 ? 2 * align_up(ctb) : 0));
 }
 
 extern "C" {
@@ -758,6 +884,35 @@ int rpa_plan_create(rpa_ctx *ctx, const rpa_cell *cell, const rpa_lri_blocks *bl
       p->groups.push_back(pg);
     }
   }
+  // class code and work estimate of every item for the single fused launch: K(R1) slices of U
+  // times the MFMA work of one slice in the item's class, plus the Z contraction; the list runs
+  // from the largest item down, so the last workgroups of a launch take the smallest items
+  {
+    const size_t ni = p->itemU.size();
+    p->item_cls.assign(ni, 0);
+    std::vector<double> cost(ni, 0.0);
+    for (const PlanGroup &g : p->groups) {
+      const int ks = fused_bf16_ks_class(g.js);
+      for (int i = g.start; i < g.start + g.count; ++i) {
+        p->item_cls[i] = single_class(g.mt, ks, g.hc);
+        const int U = p->itemU[i], V = p->itemV[i];
+        cost[i] = (double)p->nslices[U] * (ks * g.hc + g.mt * g.hc) + 0.25 * p->nao[U] * p->nao[V] * g.mt;
+      }
+    }
+    p->item_order.resize(ni);
+    for (size_t i = 0; i < ni; ++i) p->item_order[i] = (int)i;
+    std::stable_sort(p->item_order.begin(), p->item_order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+    // 4-wave units: the first 64 ABF columns of V, and the rest where V has more
+    for (int i : p->item_order) {
+      p->half_order.push_back(2 * i);
+      if (p->naux[p->itemV[i]] > 64) p->half_order.push_back(2 * i + 1);
+    }
+    std::stable_sort(p->half_order.begin(), p->half_order.end(), [&](int x, int y) {
+      const double cx = cost[x >> 1] * (p->naux[p->itemV[x >> 1]] > 64 ? 0.5 : 1.0);
+      const double cy = cost[y >> 1] * (p->naux[p->itemV[y >> 1]] > 64 ? 0.5 : 1.0);
+      return cx > cy;
+    });
+  }
   for (int a = 0; a < na; ++a)
     if (p->nbr_start[a + 1] - p->nbr_start[a] > kMaxNbr) {
       delete p;
@@ -845,6 +1000,9 @@ int rpa_plan_create(rpa_ctx *ctx, const rpa_cell *cell, const rpa_lri_blocks *bl
                s_pct = add(p->ctn_off.data(), nblk * 8), s_gsrc = add(p->gsrc.data(), p->gsrc.size() * 4),
                s_ngs = add(p->ngrp_start.data(), (na + 1) * 4), s_ng = add(p->ngrp.data(), p->ngrp.size() * 16),
                s_ngo = add(p->ngrp_off.data(), p->ngrp_off.size() * 8);
+  const size_t s_icls = add(p->item_cls.data(), p->item_cls.size() * 4),
+               s_iord = add(p->item_order.data(), p->item_order.size() * 4),
+               s_hord = add(p->half_order.data(), p->half_order.size() * 4);
   const size_t s_tVx = add(tileVx.data(), tileVx.size() * 4), s_tMx = add(tileMx.data(), tileMx.size() * 4),
                s_tNx = add(tileNx.data(), tileNx.size() * 4), s_iUx = add(itemUx.data(), itemUx.size() * 4),
                s_iVx = add(itemVx.data(), itemVx.size() * 4), s_iRx = add(itemRx.data(), itemRx.size() * 4);
@@ -900,26 +1058,21 @@ int rpa_plan_create(rpa_ctx *ctx, const rpa_cell *cell, const rpa_lri_blocks *bl
   p->items_x = PairItems{I32(s_iUx), I32(s_iVx), I32(s_iRx), (int)itemUx.size()};
   p->pack = PackTables{I64(s_pin), I64(s_pout), I64(s_pcb), I64(s_pct), I32(s_pa), I32(s_pni), I32(s_pnk), I32(s_pst),
                        nblk};
+  p->d_item_cls = I32(s_icls);
+  p->d_item_order = I32(s_iord);
+  p->d_half_order = I32(s_hord);
+
 
   // workspace: packed C (FP32 / FP64 N stage), split-BF16 C (BF16X3 fused kernel), padded G of
   // one tau, N buffer for one tau, G scale (partial maxima and the two exponents), and for the
   // split-BF16 N stage transposed G of one tau and C, hi and lo parts each
-  const size_t es = precision == RPA_FP64 ? 8 : 4;
   const size_t kViewMax = (size_t)0xffff0000u;
   const size_t gtb = (size_t)2 * nR * p->nbp * p->nbq * 2, ctb = (size_t)p->ctn_elems * 2;
   p->nbf16 = precision == RPA_BF16X3 && gtb <= kViewMax && ctb <= kViewMax;
   p->gt_bytes = p->nbf16 ? (unsigned)gtb : 0u;
   p->ct_bytes = p->nbf16 ? (unsigned)ctb : 0u;
   p->tune.nstage_kstep = p->nbf16 ? 0 : 16;
-  p->ws_cp = 0;
-  p->ws_cb = align_up(p->nbf16 ? 0 : p->cp_elems * es);
-  p->ws_g = align_up(p->ws_cb + (precision == RPA_BF16X3 ? (size_t)p->cb_elems * 2 : 0));
-  const size_t gbytes = 2 * (size_t)nR * p->nbp * p->nbp * es;
-  p->ws_n = align_up(p->ws_g + gbytes);
-  p->ws_sc = align_up(p->ws_n + (size_t)p->n_elems * es);
-  p->ws_gt = align_up(p->ws_sc + 2 * kGscaleBlocks * sizeof(double) + 2 * sizeof(int));
-  p->ws_ct = align_up(p->ws_gt + (p->nbf16 ? 2 * align_up(gtb) : 0));
-  p->ws_total = align_up(p->ws_ct + (p->nbf16 ? 2 * align_up(ctb) : 0));
+  plan_layout(p);
   *workspace_bytes = p->ws_total;
   *out = p;
   return RPA_OK;
@@ -927,13 +1080,98 @@ int rpa_plan_create(rpa_ctx *ctx, const rpa_cell *cell, const rpa_lri_blocks *bl
 
 int rpa_plan_destroy(rpa_plan *p) {
   if (!p) return RPA_ERR_ARG;
-  if (p->dtab) {
+  if (p->dtab || p->dscr) {
     // the tables may still be read by queued kernels of this plan
     hipSetDevice(p->device);
     hipDeviceSynchronize();
-    hipFree(p->dtab);
+    if (p->dtab) hipFree(p->dtab);
+    if (p->dscr) hipFree(p->dscr);
   }
   delete p;
+  return RPA_OK;
+}
+
+// Screening buffer for p->slots tau points: bounds gb, gn and (g, cut) per slot, statistics of
+// every tau.  Waits for the device before freeing an older buffer.
+static int screen_alloc(rpa_plan *p) {
+  const size_t nb3 = (size_t)p->natoms * p->natoms * p->nR;
+  const size_t b_gb = align_up(p->slots * nb3 * sizeof(double)), b_gc = align_up(2 * p->slots * sizeof(double));
+  const size_t b_st = align_up((size_t)p->ntau * p->itemU.size() * 3 * sizeof(int));
+  HIP_TRY(p->ctx, hipSetDevice(p->device));
+  if (p->dscr) {
+    HIP_TRY(p->ctx, hipDeviceSynchronize());
+    HIP_TRY(p->ctx, hipFree(p->dscr));
+    p->dscr = nullptr;
+  }
+  HIP_TRY(p->ctx, hipMalloc(&p->dscr, 2 * b_gb + b_gc + b_st));
+  char *d = (char *)p->dscr;
+  p->scr_gb = (double *)d;
+  p->scr_gn = (double *)(d + b_gb);
+  p->scr_gc = (double *)(d + 2 * b_gb);
+  p->scr_stats = (int *)(d + 2 * b_gb + b_gc);
+  return RPA_OK;
+}
+
+int rpa_plan_set_screening(rpa_plan *p, double theta) {
+  if (!p) return RPA_ERR_ARG;
+  if (!(theta >= 0.0) || !std::isfinite(theta)) return fail(p->ctx, RPA_ERR_ARG, "theta must be finite and >= 0");
+  if (theta > 0.0 && !p->dscr) {
+    const int rc = screen_alloc(p);
+    if (rc != RPA_OK) return rc;
+  }
+  p->theta = theta;
+  p->scr_valid = false;
+  return RPA_OK;
+}
+
+int rpa_plan_set_tau_batch(rpa_plan *p, int ntau_per_launch, size_t *workspace_bytes) {
+  if (!p) return RPA_ERR_ARG;
+  if (!workspace_bytes) return fail(p->ctx, RPA_ERR_ARG, "null argument");
+  if (ntau_per_launch < 1 || ntau_per_launch > p->ntau)
+    return fail(p->ctx, RPA_ERR_ARG, "tau points per launch must be in [1, ntau]");
+  p->slots = ntau_per_launch;
+  plan_layout(p);
+  if (p->dscr) {
+    const int rc = screen_alloc(p);
+    if (rc != RPA_OK) return rc;
+  }
+  p->scr_valid = false;
+  *workspace_bytes = p->ws_total;
+  return RPA_OK;
+}
+
+int rpa_plan_workspace_bytes(const rpa_plan *p, size_t *workspace_bytes) {
+  if (!p || !workspace_bytes) return RPA_ERR_ARG;
+  *workspace_bytes = p->ws_total;
+  return RPA_OK;
+}
+
+int rpa_plan_screening_stats(rpa_plan *p, long long *out) {
+  if (!p) return RPA_ERR_ARG;
+  if (!out) return fail(p->ctx, RPA_ERR_ARG, "null argument");
+  if (!p->scr_valid) return fail(p->ctx, RPA_ERR_ARG, "no screened build since the threshold was set");
+  const size_t nitems = p->itemU.size();
+  std::vector<int> h((size_t)p->ntau * nitems * 3);
+  HIP_TRY(p->ctx, hipSetDevice(p->device));
+  HIP_TRY(p->ctx, hipStreamSynchronize(p->ctx->stream));
+  HIP_TRY(p->ctx, hipMemcpy(h.data(), p->scr_stats, h.size() * sizeof(int), hipMemcpyDeviceToHost));
+  long long ek = 0, sk = 0, zk = 0, et = 0, st = 0;
+  for (size_t i = 0; i < h.size(); i += 3) {
+    ek += h[i];
+    sk += h[i + 1];
+    zk += h[i + 2];
+  }
+  for (size_t i = 0; i < nitems; ++i) {
+    const int U = p->itemU[i];
+    et += p->nbr_start[U + 1] - p->nbr_start[U];
+    st += p->nslices[U];
+  }
+  out[0] = ek;
+  out[1] = et * p->ntau;
+  out[2] = sk;
+  out[3] = st * p->ntau;
+  out[4] = zk;
+  out[5] = (long long)nitems * p->ntau;
   return RPA_OK;
 }
 
@@ -947,6 +1185,7 @@ int rpa_plan_flops(const rpa_plan *p, double *alg, double *exec) {
 static bool tuning_valid(const rpa_plan *p, const rpa_tuning &t) {
   if (t.nstage_order != 0 && t.nstage_order != 1) return false;
   if (t.fused_order != 0 && t.fused_order != 1) return false;
+  if (t.fused_single != 0 && !((t.fused_single == 1 || t.fused_single == 2) && p->prec == RPA_BF16X3)) return false;
   return p->nbf16 ? t.nstage_kstep == 0 : (t.nstage_kstep == 16 || t.nstage_kstep == 32);
 }
 
@@ -960,8 +1199,10 @@ int rpa_plan_set_tuning(rpa_plan *p, const rpa_tuning *t) {
   if (!p) return RPA_ERR_ARG;
   if (!t) return fail(p->ctx, RPA_ERR_ARG, "null tuning");
   if (!tuning_valid(p, *t))
-    return fail(p->ctx, RPA_ERR_ARG, "tuning out of range (orders 0 or 1; K step 16 or 32, 0 for the split-BF16 N stage)");
-  p->tune = rpa_tuning{t->nstage_order, t->nstage_kstep, t->fused_order, 0, 0.0, 0.0};
+    return fail(p->ctx, RPA_ERR_ARG,
+                "tuning out of range (orders 0 or 1; K step 16 or 32, 0 for the split-BF16 N stage; single fused "
+                "launch 0, or 1 or 2 on split-BF16 plans)");
+  p->tune = rpa_tuning{t->nstage_order, t->nstage_kstep, t->fused_order, 0, 0.0, 0.0, t->fused_single};
   return RPA_OK;
 }
 
@@ -1137,6 +1378,28 @@ int build_green_tau(rpa_ctx *ctx, int nk, int nb, int nocc, double mu, int ntau,
       HIP_TRY(ctx, launch_zgemm(g, nk, s));
       HIP_TRY(ctx, launch_k2r_real(ctx->params, nR, nk, m, W, (occ ? G_occ : G_un) + t * gstride, s));
     }
+  return RPA_OK;
+}
+
+int rpa_check_green_symmetry(rpa_ctx *ctx, int ntau, const int mesh[3], int nb, const double *G_occ,
+                             const double *G_un, double tol, double *rel_dev) {
+  if (!ctx) return RPA_ERR_ARG;
+  if (!mesh || !G_occ || !G_un || ntau <= 0 || nb <= 0 || !(tol >= 0.0))
+    return fail(ctx, RPA_ERR_ARG, "bad argument");
+  for (int d = 0; d < 3; ++d)
+    if (mesh[d] <= 0) return fail(ctx, RPA_ERR_ARG, "mesh must be positive");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  double *d = nullptr, h[2] = {0.0, 0.0};
+  HIP_TRY(ctx, hipMalloc(&d, 2 * sizeof(double)));
+  hipError_t e = launch_green_symmetry(G_occ, G_un, ntau, mesh, nb, d, ctx->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(h, d, 2 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  (void)hipFree(d);
+  if (e != hipSuccess) return fail(ctx, RPA_ERR_HIP, std::string("symmetry check: ") + hipGetErrorString(e));
+  const double rel = h[1] > 0.0 ? h[0] / h[1] : h[0];
+  if (rel_dev) *rel_dev = rel;
+  if (!(rel <= tol))
+    return fail(ctx, RPA_ERR_ARG, "G(-R) differs from G(R)^T: relative deviation " + std::to_string(rel));
   return RPA_OK;
 }
 

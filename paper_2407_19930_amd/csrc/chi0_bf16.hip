@@ -10,6 +10,7 @@
 // The N intermediate stays FP32 and is split in registers.  It comes from the split-BF16 N stage
 // at the end of this file, or from the FP32 N stage when its operands do not fit 32-bit views.
 #include "chi0_kernels.h"
+#include "item_table.h"
 
 namespace {
 
@@ -78,45 +79,53 @@ __global__ __launch_bounds__(256) void pack_cb_kernel(PackTables pt, const doubl
 
 constexpr int FB_THREADS = 512;
 
-// MT mu-tiles of U, KS O-GEMM steps of 32 over j' < 2 n_V, HC i-tiles of U (n_U <= 16 HC).
-template <int MT, int KS, int HC>
-__global__ __launch_bounds__(FB_THREADS) void fused_bf16_kernel(Chi0Tables tb, PairItems items,
-                                                                const float *__restrict__ Gp,
-                                                                const __bf16 *__restrict__ Cb,
-                                                                const float *__restrict__ Nbuf, double negs,
-                                                                const int *__restrict__ gexp,
-                                                                double *__restrict__ chi) {
+// LDS row stride (dwords) of the staged C slices: hi, lo slots and 4 dwords of padding
+template <int HC> constexpr int fb_row_stride() { return 16 * HC + 4; }
+
+// LDS of one workgroup of the fused kernel, carved by the kernel that runs the body: two C slice
+// buffers of kMaxNaux rows (Cs), the item's neighbour table and its scratch.
+struct FusedLds {
+  unsigned *Cs;
+  long long *nbr_c, *nbr_n;
+  int *nbr_k, *nbr_g, *pos, *meta;
+};
+
+// One item (U <= V, R) of one tau: MT mu-tiles of U, KS O-GEMM steps of 32 over j' < 2 n_V, HC
+// i-tiles of U (n_U <= 16 HC), NW waves of 64 lanes.  Wave w owns the 16 ABF columns nu of V in
+// tile half NW + w, so a workgroup of 8 waves covers up to 128 columns and one of 4 waves the
+// half `half` of them (two workgroups per item when a_V > 64).  Every thread of the workgroup
+// runs it; it leaves no barrier pending, and the caller must synchronise before the LDS is used
+// again.  stat: index of the item's statistics record (Screen::stats).
+template <int MT, int KS, int HC, int NW>
+__device__ __forceinline__ void fused_bf16_body(const Chi0Tables &tb, int U, int V, int R, int half,
+                                                const float *__restrict__ Gp, const __bf16 *__restrict__ Cb,
+                                                const float *__restrict__ Nbuf, double negs,
+                                                const int *__restrict__ gexp, const Screen &sc, int stat,
+                                                double *__restrict__ chi, const FusedLds &lds) {
+  constexpr int NT = 64 * NW;            // threads of the workgroup
   constexpr int KW = 4 * HC;             // contraction values per lane in the chi GEMM
   constexpr int S = 16 * HC;             // slots per C row and part (hi, lo)
-  constexpr int RS = 16 * HC + 4;        // LDS row stride in dwords: hi, lo, 4 dwords of padding
+  constexpr int RS = fb_row_stride<HC>();
   constexpr int CH = 4 * HC;             // 16-byte chunks per C row
   constexpr int CG = 4;                  // mu-tiles whose C fragments are all read before the O GEMM
   typedef typename BfMfma<KW>::vec CVec;
   typedef typename BfMfma<8>::vec NVec;
-  __shared__ __align__(16) unsigned Cs[2][kMaxNaux * RS];
-  __shared__ long long nbr_c[kMaxNbr], nbr_n[kMaxNbr];
-  __shared__ int nbr_k[kMaxNbr], nbr_g[kMaxNbr];
+  unsigned *const Cs0 = lds.Cs, *const Cs1 = lds.Cs + kMaxNaux * RS;
+  long long *const nbr_c = lds.nbr_c, *const nbr_n = lds.nbr_n;
+  int *const nbr_k = lds.nbr_k, *const nbr_g = lds.nbr_g;
 
-  const int item = blockIdx.x;
-  const int U = items.U[item], V = items.V[item], R = items.R[item];
   const int nU = tb.nao[U], aU = tb.naux[U], nV = tb.nao[V], aV = tb.naux[V];
   const int natoms = tb.natoms, nR = tb.nR, nbp = tb.nbp;
   const size_t plane = (size_t)nbp * nbp;
-  const int tid = threadIdx.x, lane = tid & 63, w = uniform(tid >> 6);
+  const int tid = threadIdx.x, lane = tid & 63, w = uniform(half * NW + (tid >> 6));
   const int col = lane & 15, grp = lane >> 4;
   const int nu = w * 16 + col;
   const bool wave_active = w * 16 < aV;
   const bool nu_ok = nu < aV;
-  const int e0 = tb.nbr_start[U], e1 = tb.nbr_start[U + 1];
-  const int ne = e1 - e0;
-
-  for (int e = tid; e < ne; e += FB_THREADS) {
-    const int K = tb.nbr_K[e0 + e];
-    nbr_k[e] = tb.nao[K];
-    nbr_c[e] = tb.nbr_cb[e0 + e];
-    nbr_n[e] = tb.noff[((size_t)V * natoms + K) * nR + tb.bvk.sub(tb.nbr_R1[e0 + e], R)];
-    nbr_g[e] = tb.nbr_run_end[e0 + e] - e0;   // end of the run of entries with the same atom K
-  }
+  // neighbour table (the entries whose M terms the screening keeps; all without screening)
+  const int3 kept = item_table<NT>(tb, sc, tb.nbr_cb, U, V, R, nbr_c, nbr_n, nbr_k, nbr_g, lds.pos, lds.meta);
+  const int ne = kept.x;
+  item_stats(sc, stat, kept);
 
   // A operand of the O GEMM, split: A[i][j'] = G^un_ij(R) for j' = j < n_V, G^occ_ij(R) for
   // j' = n_V + j; lane (col, grp) holds i = 16 h + col, j' = 32 ks + 8 grp + e
@@ -162,7 +171,7 @@ __global__ __launch_bounds__(FB_THREADS) void fused_bf16_kernel(Chi0Tables tb, P
   {
     const float *NA = Nbuf + tb.noff[((size_t)U * natoms + V) * nR + R];
     const float *NB = Nbuf + tb.noff[((size_t)V * natoms + U) * nR + negR];
-    if (wave_active) {
+    if (wave_active && kept.z) {
       const int F = 2 * nU * nV;
       // views of the two N blocks (elements outside them read zero): the loads of ZB iterations
       // are issued together and waited for once; each accumulator sees the same MFMA sequence
@@ -202,20 +211,21 @@ __global__ __launch_bounds__(FB_THREADS) void fused_bf16_kernel(Chi0Tables tb, P
   __syncthreads();   // neighbour table visible
 
   // C slices: aU rows of CH 16-byte chunks, copied chunk for chunk into LDS rows of RS dwords.
-  // HC * 512 chunks cover all kMaxNaux rows; rows past aU read zero.
+  // NLD loads of NT threads cover the CH kMaxNaux chunks of all rows; rows past aU read zero.
+  constexpr int NLD = CH * kMaxNaux / NT;
   const unsigned sliceBytes = (unsigned)(aU * CH * 16);
   const size_t sliceElems = (size_t)aU * 2 * S;
   auto load_slice = [&](const __bf16 *src, u4 *rc) {
     const __amdgpu_buffer_rsrc_t r = buffer_view(src, sliceBytes);
 #pragma unroll
-    for (int q = 0; q < HC; ++q)
-      rc[q] = __builtin_bit_cast(u4, __builtin_amdgcn_raw_buffer_load_b128(r, (unsigned)((tid + q * FB_THREADS) * 16), 0, 0));
+    for (int q = 0; q < NLD; ++q)
+      rc[q] = __builtin_bit_cast(u4, __builtin_amdgcn_raw_buffer_load_b128(r, (unsigned)((tid + q * NT) * 16), 0, 0));
   };
   auto store_slice = [&](int buf, const u4 *rc) {
 #pragma unroll
-    for (int q = 0; q < HC; ++q) {
-      const int c = tid + q * FB_THREADS;
-      *reinterpret_cast<u4 *>(&Cs[buf][(c / CH) * RS + 4 * (c % CH)]) = rc[q];
+    for (int q = 0; q < NLD; ++q) {
+      const int c = tid + q * NT;
+      *reinterpret_cast<u4 *>(&(buf ? Cs1 : Cs0)[(c / CH) * RS + 4 * (c % CH)]) = rc[q];
     }
   };
   // N rows (FP32): lane (nu, grp) holds j' = 32 ks + 8 grp + e; rows j' >= 2 n_V read zero
@@ -269,7 +279,7 @@ __global__ __launch_bounds__(FB_THREADS) void fused_bf16_kernel(Chi0Tables tb, P
     load_n(Nbuf + uniform(nbr_n[ea]) + (size_t)ka * nstride, nb);
   };
   bool fcur = false;   // fold after the slice being computed
-  u4 rc[HC];
+  u4 rc[NLD];
   // slice t: loads of slice t + 1's C (into rc) and of slice t + 2's N rows (into nbld), O GEMM and
   // chi += C O on the N rows of t (nbcur) and the C slice of t in LDS buffer cur, then rc to LDS.
   // live: t is a slice; live1: t + 1 is a slice.
@@ -281,7 +291,7 @@ __global__ __launch_bounds__(FB_THREADS) void fused_bf16_kernel(Chi0Tables tb, P
     if (live && wave_active) {
       // C fragments of the first M0 mu-tiles (all of them up to CG) first: their LDS reads
       // complete under the O GEMM; the others are read before the chi MFMAs
-      const unsigned *cs = &Cs[cur][col * RS + grp * (KW / 2)];
+      const unsigned *cs = &(cur ? Cs1 : Cs0)[col * RS + grp * (KW / 2)];
       constexpr int M0 = MT <= CG ? MT : CG - 1, M1 = MT - M0 > 0 ? MT - M0 : 1;
       CVec ch0[M0], cl0[M0];
 #pragma unroll
@@ -346,7 +356,7 @@ __global__ __launch_bounds__(FB_THREADS) void fused_bf16_kernel(Chi0Tables tb, P
     __syncthreads();
   };
 
-  const int nsl = tb.nslices[U];
+  const int nsl = kept.y;
   if (ne > 0) {
     g1 = uniform(nbr_g[0]);
     load_at(nb0);
@@ -367,7 +377,7 @@ __global__ __launch_bounds__(FB_THREADS) void fused_bf16_kernel(Chi0Tables tb, P
 
   // ---- epilogue: chi_UV(R) and chi_VU(-R) = chi_UV(R)^T, G scale removed
   if (!wave_active || !nu_ok) return;
-  const double sc = ldexp(negs, -(gexp[0] + gexp[1]));
+  const double scale = ldexp(negs, -(gexp[0] + gexp[1]));
   const size_t N = tb.nauxtot;
   const int au0 = tb.aux_off[U], av0 = tb.aux_off[V];
 #pragma unroll
@@ -376,7 +386,7 @@ __global__ __launch_bounds__(FB_THREADS) void fused_bf16_kernel(Chi0Tables tb, P
     for (int r = 0; r < 4; ++r) {
       const int mu = 16 * m + Mfma<float>::row(grp, r);
       if (mu < aU) {
-        const double v = sc * acc64[m][r];
+        const double v = scale * acc64[m][r];
         chi[((size_t)R * N + au0 + mu) * N + av0 + nu] = v;
         if (U != V) chi[((size_t)negR * N + av0 + nu) * N + au0 + mu] = v;
       }
@@ -384,21 +394,80 @@ __global__ __launch_bounds__(FB_THREADS) void fused_bf16_kernel(Chi0Tables tb, P
   }
 }
 
+// Per-class launch: workgroup b runs item b of the list.
+template <int MT, int KS, int HC>
+__global__ __launch_bounds__(FB_THREADS) void fused_bf16_kernel(Chi0Tables tb, PairItems items,
+                                                                const float *__restrict__ Gp,
+                                                                const __bf16 *__restrict__ Cb,
+                                                                const float *__restrict__ Nbuf, double negs,
+                                                                const int *__restrict__ gexp, Screen sc,
+                                                                double *__restrict__ chi) {
+  __shared__ __align__(16) unsigned Cs[2 * kMaxNaux * fb_row_stride<HC>()];
+  __shared__ long long nbr_c[kMaxNbr], nbr_n[kMaxNbr];
+  __shared__ int nbr_k[kMaxNbr], nbr_g[kMaxNbr], nbr_pos[kMaxNbr + 1], nbr_meta[3];
+  const FusedLds lds{Cs, nbr_c, nbr_n, nbr_k, nbr_g, nbr_pos, nbr_meta};
+  const int item = blockIdx.x;
+  fused_bf16_body<MT, KS, HC, 8>(tb, items.U[item], items.V[item], items.R[item], 0, Gp, Cb, Nbuf, negs, gexp, sc,
+                                 item, chi, lds);
+}
+
+// One launch over the work of several tau points and every template class.  Work unit u of slot
+// w / nunits is a.order[w % nunits]: with 8-wave workgroups an item, with 4-wave workgroups an
+// item and the half of its ABF columns of V (code 2 item + half; only halves with columns).  The
+// units of a slot come in order of decreasing work, and the hardware hands the workgroups to the
+// compute units in index order as they free up, so the launch ends on the smallest units.  The
+// item's class code (mt - 1) 4 + (ks - 1) 2 + (hc - 1) picks the instantiation of the body.
+template <int MT, int KS, int HC, int NW>
+__device__ __forceinline__ void single_item(const Chi0Tables &tb, const SingleLaunch &a, int item, int half, int slot,
+                                            const FusedLds &lds) {
+  Screen sc{nullptr, nullptr, nullptr, nullptr};
+  if (a.gb) {
+    const size_t nb3 = (size_t)tb.natoms * tb.natoms * tb.nR;
+    sc = Screen{a.gb + slot * nb3, a.gn + slot * nb3, a.gc + 2 * slot,
+                a.stats ? a.stats + (size_t)slot * a.stats_stride : nullptr};
+  }
+  fused_bf16_body<MT, KS, HC, NW>(tb, a.U[item], a.V[item], a.R[item], half, a.Gp + slot * a.gp_stride,
+                                  reinterpret_cast<const __bf16 *>(a.Cb), a.Nbuf + slot * a.n_stride, a.negs,
+                                  a.gexp + 2 * slot, sc, item, a.chi + slot * a.chi_stride, lds);
+}
+
+template <int NW>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2, 2))) void fused_bf16_single(
+    Chi0Tables tb, SingleLaunch a) {
+  __shared__ __align__(16) unsigned Cs[2 * kMaxNaux * fb_row_stride<2>()];
+  __shared__ long long nbr_c[kMaxNbr], nbr_n[kMaxNbr];
+  __shared__ int nbr_k[kMaxNbr], nbr_g[kMaxNbr], nbr_pos[kMaxNbr + 1], nbr_meta[3];
+  const FusedLds lds{Cs, nbr_c, nbr_n, nbr_k, nbr_g, nbr_pos, nbr_meta};
+  const int w = blockIdx.x;
+  const int slot = w / a.nitems;
+  const int code = a.order[w - slot * a.nitems];
+  const int item = NW == 8 ? code : code >> 1, half = NW == 8 ? 0 : code & 1;
+  switch (a.cls[item]) {
+#define RPA_CLS(mt, ks, hc) \
+  case (mt - 1) * 4 + (ks - 1) * 2 + (hc - 1): single_item<mt, ks, hc, NW>(tb, a, item, half, slot, lds); break;
+#define RPA_CLS_MT(mt) RPA_CLS(mt, 1, 1) RPA_CLS(mt, 1, 2) RPA_CLS(mt, 2, 1) RPA_CLS(mt, 2, 2)
+    RPA_CLS_MT(1) RPA_CLS_MT(2) RPA_CLS_MT(3) RPA_CLS_MT(4) RPA_CLS_MT(5) RPA_CLS_MT(6) RPA_CLS_MT(7) RPA_CLS_MT(8)
+#undef RPA_CLS_MT
+#undef RPA_CLS
+    default: break;
+  }
+}
+
 template <int MT, int KS, int HC>
 void launch_one_bf16(const Chi0Tables &tb, const PairItems &items, const float *Gp, const __bf16 *Cb,
-                     const float *Nbuf, double negs, const int *gexp, double *chi, hipStream_t s) {
+                     const float *Nbuf, double negs, const int *gexp, const Screen &sc, double *chi, hipStream_t s) {
   hipLaunchKernelGGL((fused_bf16_kernel<MT, KS, HC>), dim3(items.count), dim3(FB_THREADS), 0, s, tb, items, Gp, Cb,
-                     Nbuf, negs, gexp, chi);
+                     Nbuf, negs, gexp, sc, chi);
 }
 
 template <int MT>
 hipError_t launch_ks_hc(int ks, int hc, const Chi0Tables &tb, const PairItems &items, const float *Gp,
-                        const __bf16 *Cb, const float *Nbuf, double negs, const int *gexp, double *chi,
-                        hipStream_t s) {
-  if (ks == 1 && hc == 1) launch_one_bf16<MT, 1, 1>(tb, items, Gp, Cb, Nbuf, negs, gexp, chi, s);
-  else if (ks == 1 && hc == 2) launch_one_bf16<MT, 1, 2>(tb, items, Gp, Cb, Nbuf, negs, gexp, chi, s);
-  else if (ks == 2 && hc == 1) launch_one_bf16<MT, 2, 1>(tb, items, Gp, Cb, Nbuf, negs, gexp, chi, s);
-  else if (ks == 2 && hc == 2) launch_one_bf16<MT, 2, 2>(tb, items, Gp, Cb, Nbuf, negs, gexp, chi, s);
+                        const __bf16 *Cb, const float *Nbuf, double negs, const int *gexp, const Screen &sc,
+                        double *chi, hipStream_t s) {
+  if (ks == 1 && hc == 1) launch_one_bf16<MT, 1, 1>(tb, items, Gp, Cb, Nbuf, negs, gexp, sc, chi, s);
+  else if (ks == 1 && hc == 2) launch_one_bf16<MT, 1, 2>(tb, items, Gp, Cb, Nbuf, negs, gexp, sc, chi, s);
+  else if (ks == 2 && hc == 1) launch_one_bf16<MT, 2, 1>(tb, items, Gp, Cb, Nbuf, negs, gexp, sc, chi, s);
+  else if (ks == 2 && hc == 2) launch_one_bf16<MT, 2, 2>(tb, items, Gp, Cb, Nbuf, negs, gexp, sc, chi, s);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }
@@ -416,19 +485,19 @@ hipError_t launch_pack_cb(const PackTables &pt, const double *C, uint16_t *Cb, l
 }
 
 hipError_t launch_fused_bf16(const Chi0Tables &tb, const PairItems &items, int mt, int ks, int hc, const float *Gp,
-                             const uint16_t *Cb, const float *Nbuf, double negs, const int *gexp, double *chi,
-                             hipStream_t s) {
+                             const uint16_t *Cb, const float *Nbuf, double negs, const int *gexp, const Screen &sc,
+                             double *chi, hipStream_t s) {
   if (items.count == 0) return hipSuccess;
   const __bf16 *cb = reinterpret_cast<const __bf16 *>(Cb);
   switch (mt) {
-    case 1: return launch_ks_hc<1>(ks, hc, tb, items, Gp, cb, Nbuf, negs, gexp, chi, s);
-    case 2: return launch_ks_hc<2>(ks, hc, tb, items, Gp, cb, Nbuf, negs, gexp, chi, s);
-    case 3: return launch_ks_hc<3>(ks, hc, tb, items, Gp, cb, Nbuf, negs, gexp, chi, s);
-    case 4: return launch_ks_hc<4>(ks, hc, tb, items, Gp, cb, Nbuf, negs, gexp, chi, s);
-    case 5: return launch_ks_hc<5>(ks, hc, tb, items, Gp, cb, Nbuf, negs, gexp, chi, s);
-    case 6: return launch_ks_hc<6>(ks, hc, tb, items, Gp, cb, Nbuf, negs, gexp, chi, s);
-    case 7: return launch_ks_hc<7>(ks, hc, tb, items, Gp, cb, Nbuf, negs, gexp, chi, s);
-    case 8: return launch_ks_hc<8>(ks, hc, tb, items, Gp, cb, Nbuf, negs, gexp, chi, s);
+    case 1: return launch_ks_hc<1>(ks, hc, tb, items, Gp, cb, Nbuf, negs, gexp, sc, chi, s);
+    case 2: return launch_ks_hc<2>(ks, hc, tb, items, Gp, cb, Nbuf, negs, gexp, sc, chi, s);
+    case 3: return launch_ks_hc<3>(ks, hc, tb, items, Gp, cb, Nbuf, negs, gexp, sc, chi, s);
+    case 4: return launch_ks_hc<4>(ks, hc, tb, items, Gp, cb, Nbuf, negs, gexp, sc, chi, s);
+    case 5: return launch_ks_hc<5>(ks, hc, tb, items, Gp, cb, Nbuf, negs, gexp, sc, chi, s);
+    case 6: return launch_ks_hc<6>(ks, hc, tb, items, Gp, cb, Nbuf, negs, gexp, sc, chi, s);
+    case 7: return launch_ks_hc<7>(ks, hc, tb, items, Gp, cb, Nbuf, negs, gexp, sc, chi, s);
+    case 8: return launch_ks_hc<8>(ks, hc, tb, items, Gp, cb, Nbuf, negs, gexp, sc, chi, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -505,12 +574,17 @@ __global__ __launch_bounds__(NB_THREADS) void nstage_bf16_kernel(Chi0Tables tb, 
                                                                   const __bf16 *__restrict__ GTl, unsigned gt_bytes,
                                                                   const __bf16 *__restrict__ Cth,
                                                                   const __bf16 *__restrict__ Ctl, unsigned ct_bytes,
-                                                                  float *__restrict__ Nbuf) {
+                                                                  float *__restrict__ Nbuf, size_t gt_slot,
+                                                                  size_t n_slot) {
   // [buffer][part hi/lo][128 rows x NB_RS]
   __shared__ __align__(16) __bf16 As[2][2][128 * NB_RS];
   __shared__ __align__(16) __bf16 Bs[2][2][128 * NB_RS];
 
   const int t = blockIdx.x;
+  // tau slot of the launch
+  GTh += (size_t)blockIdx.y * gt_slot;
+  GTl += (size_t)blockIdx.y * gt_slot;
+  Nbuf += (size_t)blockIdx.y * n_slot;
   const int V = tiles.V[t], m0 = tiles.m0[t], n0 = tiles.n0[t];
   const int nV = tb.nao[V], aV = tb.naux[V];
   const int NV = nV * aV;
@@ -675,10 +749,22 @@ hipError_t launch_pad_gt(const double *Gocc, const double *Gun, int nR, int nb, 
 
 hipError_t launch_nstage_bf16(const Chi0Tables &tb, const NTiles &tiles, const uint16_t *GTh, const uint16_t *GTl,
                               unsigned gt_bytes, const uint16_t *Cth, const uint16_t *Ctl, unsigned ct_bytes,
-                              float *Nbuf, hipStream_t s) {
-  if (tiles.count == 0) return hipSuccess;
-  hipLaunchKernelGGL(nstage_bf16_kernel, dim3(tiles.count), dim3(NB_THREADS), 0, s, tb, tiles,
+                              float *Nbuf, int nslots, size_t gt_slot, size_t n_slot, hipStream_t s) {
+  if (tiles.count == 0 || nslots <= 0) return hipSuccess;
+  hipLaunchKernelGGL(nstage_bf16_kernel, dim3(tiles.count, nslots), dim3(NB_THREADS), 0, s, tb, tiles,
                      reinterpret_cast<const __bf16 *>(GTh), reinterpret_cast<const __bf16 *>(GTl), gt_bytes,
-                     reinterpret_cast<const __bf16 *>(Cth), reinterpret_cast<const __bf16 *>(Ctl), ct_bytes, Nbuf);
+                     reinterpret_cast<const __bf16 *>(Cth), reinterpret_cast<const __bf16 *>(Ctl), ct_bytes, Nbuf,
+                     gt_slot, n_slot);
+  return hipGetLastError();
+}
+
+hipError_t launch_fused_bf16_single(const Chi0Tables &tb, const SingleLaunch &a, int nw, hipStream_t s) {
+  const long long n = (long long)a.nslots * a.nitems;
+  if (n == 0) return hipSuccess;
+  if (n > 0x7fffffffLL || (nw != 8 && nw != 4)) return hipErrorInvalidValue;
+  if (nw == 8)
+    hipLaunchKernelGGL(fused_bf16_single<8>, dim3((unsigned)n), dim3(512), 0, s, tb, a);
+  else
+    hipLaunchKernelGGL(fused_bf16_single<4>, dim3((unsigned)n), dim3(256), 0, s, tb, a);
   return hipGetLastError();
 }

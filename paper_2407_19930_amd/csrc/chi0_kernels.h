@@ -35,6 +35,20 @@ struct Chi0Tables {
   Bvk bvk;
 };
 
+// Green's-function screening of one tau (the decay of G that limits the range of R, Sec. 2 after
+// Algorithm 1; the threshold on G of the case study, Sec. 6).  For every (U, V, R):
+//   gb[(U natoms + V) nR + R] = max over s, i in U, j in V of |G^s_ij(R)|,
+//   gn[(V natoms + K) nR + dR] = max over L(dL) in N[V] of gb(L, K, dR - dL),
+//   gc[0] = g = max gb, gc[1] = cut = (theta g) g.
+// A fused-kernel item (U, V, R) keeps the M terms of neighbour K(R1) of U when
+// gb(U, V, R) gn(V, K, R1 - R) >= cut and its Z terms when gn(U, V, R) gn(V, U, -R) >= cut
+// (FP64 products and comparisons).  stats (may be null): per launched item {neighbour entries
+// kept, K(R1) slices kept, Z terms kept (0 or 1)}.  Screening is off when gb is null.
+struct Screen {
+  const double *gb, *gn, *gc;
+  int *stats;
+};
+
 // Work lists.
 struct NTiles {      // N-stage output tiles: atom V, first row (s, dR, k), first column (j, nu)
   const int *V, *m0, *n0;
@@ -74,7 +88,8 @@ int fused_js_class(int nao);
 // chi is written as negs 2^-(gexp[0] + gexp[1]) times the contraction (gexp may be null).
 template <typename T>
 hipError_t launch_fused(const Chi0Tables &tb, const PairItems &items, int mt, int js, int hc, const T *Gp,
-                        const T *Cp, const T *Nbuf, double negs, const int *gexp, double *chi, hipStream_t s);
+                        const T *Cp, const T *Nbuf, double negs, const int *gexp, const Screen &sc, double *chi,
+                        hipStream_t s);
 
 // Split-BF16 (3-term) fused kernel on FP32 G and N, with C packed by launch_pack_cb (bf16 bits
 // as uint16_t); ks = O-GEMM steps of 32 for the group's js class.
@@ -86,12 +101,44 @@ hipError_t launch_pack_ctn(const PackTables &pt, const double *C, uint16_t *Cth,
                            hipStream_t s);
 hipError_t launch_pad_gt(const double *Gocc, const double *Gun, int nR, int nb, int nbp, int nbq, const int *gsrc,
                          const int *gexp, uint16_t *GTh, uint16_t *GTl, hipStream_t s);
+// nslots tau points in one launch (grid.y): slot t reads GTh/GTl + t gt_slot (elements) and
+// writes Nbuf + t n_slot (elements).
 hipError_t launch_nstage_bf16(const Chi0Tables &tb, const NTiles &tiles, const uint16_t *GTh, const uint16_t *GTl,
                               unsigned gt_bytes, const uint16_t *Cth, const uint16_t *Ctl, unsigned ct_bytes,
-                              float *Nbuf, hipStream_t s);
+                              float *Nbuf, int nslots, size_t gt_slot, size_t n_slot, hipStream_t s);
 hipError_t launch_fused_bf16(const Chi0Tables &tb, const PairItems &items, int mt, int ks, int hc, const float *Gp,
-                             const uint16_t *Cb, const float *Nbuf, double negs, const int *gexp, double *chi,
-                             hipStream_t s);
+                             const uint16_t *Cb, const float *Nbuf, double negs, const int *gexp, const Screen &sc,
+                             double *chi, hipStream_t s);
+
+// Single split-BF16 fused launch over the items of nslots tau points, every template class in one
+// launch (chi0_bf16.hip).  Per slot (tau of the launch): Gp, N, the two G-scale exponents, chi,
+// and the screening bounds and statistics, each at slot * stride from the first.
+struct SingleLaunch {
+  const int *U, *V, *R, *cls;        // per plan item; cls = single_class(mt, ks, hc)
+  const int *order;                  // [nitems] work units of a slot in launch order: items (8-wave
+                                     // workgroups) or 2 item + half (4-wave workgroups)
+  int nitems, nslots;
+  const float *Gp;
+  size_t gp_stride;
+  const uint16_t *Cb;
+  const float *Nbuf;
+  size_t n_stride;
+  const int *gexp;                   // [nslots][2]
+  double negs;
+  double *chi;
+  size_t chi_stride;
+  const double *gb, *gn, *gc;        // null: no screening; else strides natoms^2 nR, natoms^2 nR, 2
+  int *stats;                        // null or per slot stats_stride ints, record = plan item
+  size_t stats_stride;
+};
+// Class code of the single launch for (mt, ks, hc).
+inline int single_class(int mt, int ks, int hc) { return (mt - 1) * 4 + (ks - 1) * 2 + (hc - 1); }
+// nw: waves per workgroup, 8 (one workgroup per item) or 4 (one per half of an item's ABF columns)
+hipError_t launch_fused_bf16_single(const Chi0Tables &tb, const SingleLaunch &a, int nw, hipStream_t s);
+
+// Screening bounds of one tau from FP64 G (see Screen): gb, then g and cut, then gn.
+hipError_t launch_screen_norms(const Chi0Tables &tb, const double *Gocc, const double *Gun, double theta, double *gb,
+                               double *gn, double *gc, hipStream_t s);
 
 // compile-time limits of the kernels
 constexpr int kMaxNao = 32;     // NAOs per atom

@@ -18,6 +18,7 @@
 //               straight from the accumulator registers; writes chi_UV(R) and its
 //               Hermitian partner chi_VU(-R) = chi_UV(R)^T.
 #include "chi0_kernels.h"
+#include "item_table.h"
 
 namespace {
 
@@ -378,7 +379,7 @@ __global__ __launch_bounds__(FU_THREADS) void fused_kernel(Chi0Tables tb, PairIt
                                                            const T *__restrict__ Gp,
                                                            const T *__restrict__ Cp,
                                                            const T *__restrict__ Nbuf, double negs,
-                                                           const int *__restrict__ gexp,
+                                                           const int *__restrict__ gexp, Screen sc,
                                                            double *__restrict__ chi) {
   typedef typename Mfma<T>::acc Acc;
   constexpr int IP = Lds<T>::IP;
@@ -386,7 +387,7 @@ __global__ __launch_bounds__(FU_THREADS) void fused_kernel(Chi0Tables tb, PairIt
   // two C slice buffers; the element after them takes the stores of idle threads
   __shared__ __align__(16) T Cs[2 * kMaxNaux * IP + 4];
   __shared__ long long nbr_c[FU_MAXNBR], nbr_n[FU_MAXNBR];
-  __shared__ int nbr_k[FU_MAXNBR], nbr_g[FU_MAXNBR];
+  __shared__ int nbr_k[FU_MAXNBR], nbr_g[FU_MAXNBR], nbr_pos[FU_MAXNBR + 1], nbr_meta[3];
 
   const int item = blockIdx.x;
   const int U = items.U[item], V = items.V[item], R = items.R[item];
@@ -399,17 +400,11 @@ __global__ __launch_bounds__(FU_THREADS) void fused_kernel(Chi0Tables tb, PairIt
   const bool wave_active = w * 16 < aV;
   const bool nu_ok = nu < aV;
   const int hc = HC;                          // i-tiles of U (nU <= 16 HC)
-  const int e0 = tb.nbr_start[U], e1 = tb.nbr_start[U + 1];
-  const int ne = e1 - e0;
-
-  // neighbour table of this item and zeroed C buffers
-  for (int e = tid; e < ne; e += FU_THREADS) {
-    const int K = tb.nbr_K[e0 + e];
-    nbr_k[e] = tb.nao[K];
-    nbr_c[e] = tb.nbr_cp[e0 + e];
-    nbr_n[e] = tb.noff[((size_t)V * natoms + K) * nR + tb.bvk.sub(tb.nbr_R1[e0 + e], R)];
-    nbr_g[e] = tb.nbr_run_end[e0 + e] - e0;   // end of the run of entries with the same atom K
-  }
+  // neighbour table of this item (the entries whose M terms the screening keeps; all without
+  // screening) and zeroed C buffers
+  const int3 kept = item_table<FU_THREADS>(tb, sc, tb.nbr_cp, U, V, R, nbr_c, nbr_n, nbr_k, nbr_g, nbr_pos, nbr_meta);
+  const int ne = kept.x;
+  item_stats(sc, blockIdx.x, kept);
   for (int e = tid; e < 2 * kMaxNaux * IP + 4; e += FU_THREADS) Cs[e] = T(0);
 
   // A operand of the O GEMM: A[i][j'] = G^un_ij(R) for j' = j, G^occ_ij(R) for j' = nV + j
@@ -452,7 +447,7 @@ __global__ __launch_bounds__(FU_THREADS) void fused_kernel(Chi0Tables tb, PairIt
   {
     const T *NA = Nbuf + tb.noff[((size_t)U * natoms + V) * nR + R];
     const T *NB = Nbuf + tb.noff[((size_t)V * natoms + U) * nR + negR];
-    if (wave_active) {
+    if (wave_active && kept.z) {
       const int F = 2 * nU * nV;
       // views of the two N blocks (elements outside them read zero): the loads of ZB iterations
       // are issued together and waited for once; each accumulator sees the same MFMA sequence
@@ -606,7 +601,7 @@ __global__ __launch_bounds__(FU_THREADS) void fused_kernel(Chi0Tables tb, PairIt
     cur ^= 1;
   };
 
-  const int nsl = tb.nslices[U];
+  const int nsl = kept.y;
   if (ne > 0) {
     load_slice(Cp + uniform(nbr_c[0]));
     store_slice(0);
@@ -621,7 +616,7 @@ __global__ __launch_bounds__(FU_THREADS) void fused_kernel(Chi0Tables tb, PairIt
 
   // ---- epilogue: chi_UV(R) and chi_VU(-R) = chi_UV(R)^T, G scale removed
   if (!wave_active || !nu_ok) return;
-  const double sc = gexp ? ldexp(negs, -(gexp[0] + gexp[1])) : negs;
+  const double scale = gexp ? ldexp(negs, -(gexp[0] + gexp[1])) : negs;
   const size_t N = tb.nauxtot;
   const int au0 = tb.aux_off[U], av0 = tb.aux_off[V];
 #pragma unroll
@@ -630,7 +625,7 @@ __global__ __launch_bounds__(FU_THREADS) void fused_kernel(Chi0Tables tb, PairIt
     for (int r = 0; r < 4; ++r) {
       const int mu = 16 * m + Mfma<T>::row(grp, r);
       if (mu < aU) {
-        const double v = sc * (kSplit ? acc64[m][r] : (double)acc[m][r]);
+        const double v = scale * (kSplit ? acc64[m][r] : (double)acc[m][r]);
         chi[((size_t)R * N + au0 + mu) * N + av0 + nu] = v;
         if (U != V) chi[((size_t)negR * N + av0 + nu) * N + au0 + mu] = v;
       }
@@ -711,25 +706,26 @@ int fused_js_class(int nao) {
 
 template <typename T, int MT, int JS>
 static void launch_one(int hc, const Chi0Tables &tb, const PairItems &items, const T *Gp, const T *Cp,
-                       const T *Nbuf, double negs, const int *gexp, double *chi, hipStream_t s) {
+                       const T *Nbuf, double negs, const int *gexp, const Screen &sc, double *chi, hipStream_t s) {
   if (hc == 1)
     hipLaunchKernelGGL((fused_kernel<T, sizeof(T) == 4, MT, JS, 1>), dim3(items.count), dim3(FU_THREADS), 0, s, tb,
-                       items, Gp, Cp, Nbuf, negs, gexp, chi);
+                       items, Gp, Cp, Nbuf, negs, gexp, sc, chi);
   else
     hipLaunchKernelGGL((fused_kernel<T, sizeof(T) == 4, MT, JS, 2>), dim3(items.count), dim3(FU_THREADS), 0, s, tb,
-                       items, Gp, Cp, Nbuf, negs, gexp, chi);
+                       items, Gp, Cp, Nbuf, negs, gexp, sc, chi);
 }
 
 template <typename T, int MT>
 static hipError_t launch_js(int js, int hc, const Chi0Tables &tb, const PairItems &items, const T *Gp, const T *Cp,
-                            const T *Nbuf, double negs, const int *gexp, double *chi, hipStream_t s) {
+                            const T *Nbuf, double negs, const int *gexp, const Screen &sc, double *chi,
+                            hipStream_t s) {
   switch (js) {
-    case 2: launch_one<T, MT, 2>(hc, tb, items, Gp, Cp, Nbuf, negs, gexp, chi, s); break;
-    case 4: launch_one<T, MT, 4>(hc, tb, items, Gp, Cp, Nbuf, negs, gexp, chi, s); break;
-    case 7: launch_one<T, MT, 7>(hc, tb, items, Gp, Cp, Nbuf, negs, gexp, chi, s); break;
-    case 10: launch_one<T, MT, 10>(hc, tb, items, Gp, Cp, Nbuf, negs, gexp, chi, s); break;
-    case 13: launch_one<T, MT, 13>(hc, tb, items, Gp, Cp, Nbuf, negs, gexp, chi, s); break;
-    case 16: launch_one<T, MT, 16>(hc, tb, items, Gp, Cp, Nbuf, negs, gexp, chi, s); break;
+    case 2: launch_one<T, MT, 2>(hc, tb, items, Gp, Cp, Nbuf, negs, gexp, sc, chi, s); break;
+    case 4: launch_one<T, MT, 4>(hc, tb, items, Gp, Cp, Nbuf, negs, gexp, sc, chi, s); break;
+    case 7: launch_one<T, MT, 7>(hc, tb, items, Gp, Cp, Nbuf, negs, gexp, sc, chi, s); break;
+    case 10: launch_one<T, MT, 10>(hc, tb, items, Gp, Cp, Nbuf, negs, gexp, sc, chi, s); break;
+    case 13: launch_one<T, MT, 13>(hc, tb, items, Gp, Cp, Nbuf, negs, gexp, sc, chi, s); break;
+    case 16: launch_one<T, MT, 16>(hc, tb, items, Gp, Cp, Nbuf, negs, gexp, sc, chi, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -737,17 +733,18 @@ static hipError_t launch_js(int js, int hc, const Chi0Tables &tb, const PairItem
 
 template <typename T>
 hipError_t launch_fused(const Chi0Tables &tb, const PairItems &items, int mt, int js, int hc, const T *Gp,
-                        const T *Cp, const T *Nbuf, double negs, const int *gexp, double *chi, hipStream_t s) {
+                        const T *Cp, const T *Nbuf, double negs, const int *gexp, const Screen &sc, double *chi,
+                        hipStream_t s) {
   if (items.count == 0) return hipSuccess;
   switch (mt) {
-    case 1: return launch_js<T, 1>(js, hc, tb, items, Gp, Cp, Nbuf, negs, gexp, chi, s);
-    case 2: return launch_js<T, 2>(js, hc, tb, items, Gp, Cp, Nbuf, negs, gexp, chi, s);
-    case 3: return launch_js<T, 3>(js, hc, tb, items, Gp, Cp, Nbuf, negs, gexp, chi, s);
-    case 4: return launch_js<T, 4>(js, hc, tb, items, Gp, Cp, Nbuf, negs, gexp, chi, s);
-    case 5: return launch_js<T, 5>(js, hc, tb, items, Gp, Cp, Nbuf, negs, gexp, chi, s);
-    case 6: return launch_js<T, 6>(js, hc, tb, items, Gp, Cp, Nbuf, negs, gexp, chi, s);
-    case 7: return launch_js<T, 7>(js, hc, tb, items, Gp, Cp, Nbuf, negs, gexp, chi, s);
-    case 8: return launch_js<T, 8>(js, hc, tb, items, Gp, Cp, Nbuf, negs, gexp, chi, s);
+    case 1: return launch_js<T, 1>(js, hc, tb, items, Gp, Cp, Nbuf, negs, gexp, sc, chi, s);
+    case 2: return launch_js<T, 2>(js, hc, tb, items, Gp, Cp, Nbuf, negs, gexp, sc, chi, s);
+    case 3: return launch_js<T, 3>(js, hc, tb, items, Gp, Cp, Nbuf, negs, gexp, sc, chi, s);
+    case 4: return launch_js<T, 4>(js, hc, tb, items, Gp, Cp, Nbuf, negs, gexp, sc, chi, s);
+    case 5: return launch_js<T, 5>(js, hc, tb, items, Gp, Cp, Nbuf, negs, gexp, sc, chi, s);
+    case 6: return launch_js<T, 6>(js, hc, tb, items, Gp, Cp, Nbuf, negs, gexp, sc, chi, s);
+    case 7: return launch_js<T, 7>(js, hc, tb, items, Gp, Cp, Nbuf, negs, gexp, sc, chi, s);
+    case 8: return launch_js<T, 8>(js, hc, tb, items, Gp, Cp, Nbuf, negs, gexp, sc, chi, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -763,6 +760,8 @@ template hipError_t launch_nstage<double>(const Chi0Tables &, const NTiles &, co
 template hipError_t launch_nstage<float>(const Chi0Tables &, const NTiles &, const float *, const float *, float *,
                                          size_t, int, hipStream_t);
 template hipError_t launch_fused<double>(const Chi0Tables &, const PairItems &, int, int, int, const double *,
-                                         const double *, const double *, double, const int *, double *, hipStream_t);
+                                         const double *, const double *, double, const int *, const Screen &,
+                                         double *, hipStream_t);
 template hipError_t launch_fused<float>(const Chi0Tables &, const PairItems &, int, int, int, const float *,
-                                        const float *, const float *, double, const int *, double *, hipStream_t);
+                                        const float *, const float *, double, const int *, const Screen &, double *,
+                                        hipStream_t);

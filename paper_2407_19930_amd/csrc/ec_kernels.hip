@@ -7,6 +7,8 @@
 // trace / identity-minus, log-diagonal and quadrature reductions.
 #include "ec_kernels.h"
 
+#include <type_traits>
+
 namespace {
 
 constexpr int ZB = 64, ZK = 16, ZT = 256;
@@ -26,6 +28,7 @@ __global__ __launch_bounds__(ZT) void zgemm_kernel(ZgemmArgs g, unsigned bytesA,
   if (g.lower_only && n0 > m0 + ZB - 1) return;
   const int gb = g.boff + bz, bi = g.binner > 0 ? g.binner : 1;
   const int go = gb / bi, gi = gb - go * bi;
+  const bool realA = g.realA && g.realA[go];   // block-uniform
   const double *A = g.A + (size_t)bz * g.strideA + (size_t)go * g.outerA + (size_t)gi * g.innerA;
   const double *B = g.B + (size_t)bz * g.strideB + (size_t)go * g.outerB + (size_t)gi * g.innerB;
   double *C = g.C + (size_t)bz * g.strideC;
@@ -84,33 +87,42 @@ __global__ __launch_bounds__(ZT) void zgemm_kernel(ZgemmArgs g, unsigned bytesA,
     store(0);
   }
   __syncthreads();
-  for (int it = 0; it < nk; ++it) {
-    const int cur = it & 1;
-    if (it + 1 < nk) load(kbeg + (it + 1) * ZK);
+  // the K loop, with four real products per complex product, or two when A is real (the same
+  // sums without the terms whose A factor is an exact zero)
+  auto kloop = [&](auto real_tag) {
+    constexpr bool kReal = decltype(real_tag)::value;
+    for (int it = 0; it < nk; ++it) {
+      const int cur = it & 1;
+      if (it + 1 < nk) load(kbeg + (it + 1) * ZK);
 #pragma unroll
-    for (int ks = 0; ks < ZK / 4; ++ks) {
-      const int kk = ks * 4 + grp;
-      double ar[2], ai[2], br[2], bi[2];
+      for (int ks = 0; ks < ZK / 4; ++ks) {
+        const int kk = ks * 4 + grp;
+        double ar[2], ai[2], br[2], bi[2];
 #pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        ar[q] = Ar[cur][kk][(wm * 32 + q * 16 + col) ^ zswz(kk)];
-        ai[q] = Ai[cur][kk][(wm * 32 + q * 16 + col) ^ zswz(kk)];
-        br[q] = Br[cur][kk][(wn * 32 + q * 16 + col) ^ zswz(kk)];
-        bi[q] = Bi[cur][kk][(wn * 32 + q * 16 + col) ^ zswz(kk)];
-      }
-#pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-          accR[a][b] = Mfma<double>::fma(ar[a], br[b], accR[a][b]);
-          accR[a][b] = Mfma<double>::fma(-ai[a], bi[b], accR[a][b]);
-          accI[a][b] = Mfma<double>::fma(ar[a], bi[b], accI[a][b]);
-          accI[a][b] = Mfma<double>::fma(ai[a], br[b], accI[a][b]);
+        for (int q = 0; q < 2; ++q) {
+          ar[q] = Ar[cur][kk][(wm * 32 + q * 16 + col) ^ zswz(kk)];
+          ai[q] = kReal ? 0.0 : Ai[cur][kk][(wm * 32 + q * 16 + col) ^ zswz(kk)];
+          br[q] = Br[cur][kk][(wn * 32 + q * 16 + col) ^ zswz(kk)];
+          bi[q] = Bi[cur][kk][(wn * 32 + q * 16 + col) ^ zswz(kk)];
         }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b) {
+            accR[a][b] = Mfma<double>::fma(ar[a], br[b], accR[a][b]);
+            if (!kReal) accR[a][b] = Mfma<double>::fma(-ai[a], bi[b], accR[a][b]);
+            accI[a][b] = Mfma<double>::fma(ar[a], bi[b], accI[a][b]);
+            if (!kReal) accI[a][b] = Mfma<double>::fma(ai[a], br[b], accI[a][b]);
+          }
+      }
+      if (it + 1 < nk) store(cur ^ 1);
+      __syncthreads();
     }
-    if (it + 1 < nk) store(cur ^ 1);
-    __syncthreads();
-  }
+  };
+  if (realA)
+    kloop(std::true_type{});
+  else
+    kloop(std::false_type{});
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -130,6 +142,19 @@ __global__ __launch_bounds__(ZT) void zgemm_kernel(ZgemmArgs g, unsigned bytesA,
           *p = o;
         }
       }
+}
+
+// real[q] &= (imaginary part == 0) over the nomega matrices of q; the flags start at 1.
+__global__ __launch_bounds__(256) void real_flags_kernel(const double *__restrict__ X, size_t mat, int nq,
+                                                         int nomega, int *__restrict__ real) {
+  const int q = blockIdx.y;
+  const size_t per = (size_t)nomega * (mat / 2);   // complex elements of q over all omega
+  bool zero = true;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < per; e += (size_t)gridDim.x * blockDim.x) {
+    const size_t w = e / (mat / 2), i = e - w * (mat / 2);
+    zero &= X[(w * nq + q) * mat + 2 * i + 1] == 0.0;
+  }
+  if (!__all(zero) && (threadIdx.x & 63) == 0) real[q] = 0;
 }
 
 // ---- Cholesky pieces (block width CB) ----
@@ -157,7 +182,7 @@ __global__ __launch_bounds__(64) void chol_diag_kernel(double *A, size_t stride,
     if (tid == 0) {
       const double d = L[j][j].x;
       if (!(d > 0.0) || !isfinite(d)) {
-        bad = 1;
+        bad = isfinite(d) ? 1 : 2;       // 1: not positive definite, 2: NaN or Inf met
         L[j][j] = make_double2(1.0, 0.0);
       } else {
         L[j][j] = make_double2(sqrt(d), 0.0);
@@ -204,7 +229,7 @@ __global__ __launch_bounds__(64) void chol_diag_kernel(double *A, size_t stride,
     const double2 x = X[j][i];
     W[e] = make_double2(x.x, -x.y);
   }
-  if (tid == 0 && bad) flags[flag_base + mtx] = 1;
+  if (tid == 0 && bad) flags[flag_base + mtx] = bad;
 }
 
 // Panel solve A21 <- A21 W for rows [p + CB, n) of every matrix (in place; each workgroup
@@ -364,6 +389,16 @@ hipError_t launch_first_flag(const int *flags, int n, int *out, hipStream_t s) {
 hipError_t launch_fill_int(int *p, size_t n, int v, hipStream_t s) {
   const int blocks = (int)std::min<size_t>((n + 255) / 256, 1024);
   hipLaunchKernelGGL(fill_int_kernel, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_real_flags(const double *X, int n, int nq, int nomega, int *real, hipStream_t s) {
+  if (nq <= 0) return hipSuccess;
+  hipError_t e = launch_fill_int(real, (size_t)nq, 1, s);
+  if (e != hipSuccess || nomega <= 0 || n <= 0) return e;
+  const size_t mat = (size_t)n * n * 2, per = (size_t)nomega * n * n;
+  const int bx = (int)std::min<size_t>((per + 255) / 256, 2048);
+  hipLaunchKernelGGL(real_flags_kernel, dim3(bx, nq), dim3(256), 0, s, X, mat, nq, nomega, real);
   return hipGetLastError();
 }
 

@@ -82,3 +82,51 @@ hipError_t launch_k2r_real(const double *ph, int nR, int nk, size_t m, const dou
   hipLaunchKernelGGL(k2r_real_kernel, dim3(blocks), dim3(256), lds, s, ph, nR, nk, m, W, G);
   return hipGetLastError();
 }
+
+namespace {
+
+__global__ void clear2_kernel(double *out) {
+  out[0] = 0.0;
+  out[1] = 0.0;
+}
+
+// One workgroup per (s, tau, R): the largest deviation from G(-R) = G(R)^T and the largest
+// entry, merged into out with integer maxima of the bit patterns (both values are >= 0).
+__global__ __launch_bounds__(256) void green_symmetry_kernel(const double *__restrict__ Gocc,
+                                                             const double *__restrict__ Gun, int ntau, int m0, int m1,
+                                                             int m2, int nb, double *__restrict__ out) {
+  const int nR = m0 * m1 * m2;
+  const int R = blockIdx.x % nR, t = (blockIdx.x / nR) % ntau, s = blockIdx.x / (nR * ntau);
+  const int c2 = R % m2, c1 = (R / m2) % m1, c0 = R / (m1 * m2);
+  const int negR = (((m0 - c0) % m0) * m1 + (m1 - c1) % m1) * m2 + (m2 - c2) % m2;
+  const double *G = (s ? Gun : Gocc) + (size_t)t * nR * nb * nb;
+  const double *A = G + (size_t)R * nb * nb, *B = G + (size_t)negR * nb * nb;
+  double dev = 0.0, mx = 0.0;
+  for (size_t e = threadIdx.x; e < (size_t)nb * nb; e += blockDim.x) {
+    const int i = (int)(e / nb), j = (int)(e % nb);
+    const double a = A[e];
+    dev = fmax(dev, fabs(B[(size_t)j * nb + i] - a));
+    mx = fmax(mx, fabs(a));
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    dev = fmax(dev, __shfl_xor(dev, off));
+    mx = fmax(mx, __shfl_xor(mx, off));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicMax(reinterpret_cast<unsigned long long *>(out), (unsigned long long)__double_as_longlong(dev));
+    atomicMax(reinterpret_cast<unsigned long long *>(out + 1), (unsigned long long)__double_as_longlong(mx));
+  }
+}
+
+}  // namespace
+
+hipError_t launch_green_symmetry(const double *Gocc, const double *Gun, int ntau, const int mesh[3], int nb,
+                                 double *out, hipStream_t s) {
+  hipLaunchKernelGGL(clear2_kernel, dim3(1), dim3(1), 0, s, out);
+  const long long blocks = 2LL * ntau * mesh[0] * mesh[1] * mesh[2];
+  if (blocks <= 0 || nb <= 0) return hipGetLastError();
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(green_symmetry_kernel, dim3((unsigned)blocks), dim3(256), 0, s, Gocc, Gun, ntau, mesh[0], mesh[1],
+                     mesh[2], nb, out);
+  return hipGetLastError();
+}

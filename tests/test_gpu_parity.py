@@ -168,7 +168,8 @@ def test_errors_are_reported():
     import torch
     from paper_2407_19930_amd import Context, Plan, RpaError, build_chi0_tau, rpa_correlation_energy, \
         rpa_ec_workspace_size
-    from paper_2407_19930_amd.binding import RPA_ERR_NOT_HPD, RPA_ERR_UNSUPPORTED, RPA_ERR_WORKSPACE
+    from paper_2407_19930_amd.binding import (RPA_ERR_ARG, RPA_ERR_NONFINITE, RPA_ERR_NOT_HPD, RPA_ERR_SHAPE,
+                                              RPA_ERR_UNSUPPORTED, RPA_ERR_WORKSPACE)
     inp = micro()
     ctx = Context(0)
     say("case error paths")
@@ -191,12 +192,73 @@ def test_errors_are_reported():
     with pytest.raises(RpaError) as e:
         rpa_correlation_energy(ctx, np.ones(nw), chi_q, vq, ws)
     assert e.value.code == RPA_ERR_NOT_HPD
+    # a NaN in chi: non-finite, not merely indefinite
+    chi_q.zero_()
+    chi_q[1, 0, 2, 5] = float("nan")
+    with pytest.raises(RpaError) as e:
+        rpa_correlation_energy(ctx, np.ones(nw), chi_q, vq, ws)
+    assert e.value.code == RPA_ERR_NONFINITE
+    # and in v(q)
+    chi_q.zero_()
+    vq[0, 3, 3] = float("inf")
+    with pytest.raises(RpaError) as e:
+        rpa_correlation_energy(ctx, np.ones(nw), chi_q, vq, ws)
+    assert e.value.code == RPA_ERR_NONFINITE
+    # inconsistent shapes: a block whose atom index is outside the cell, a mesh of zero
+    with pytest.raises(RpaError) as e:
+        Plan(ctx, inp.nao, inp.naux, inp.cell.mesh, inp.blocks.I, np.where(inp.blocks.K == 0, len(inp.nao), inp.blocks.K),
+             inp.blocks.R, inp.blocks.off, inp.ntau)
+    assert e.value.code == RPA_ERR_SHAPE
+    with pytest.raises(RpaError) as e:
+        Plan(ctx, inp.nao, inp.naux, (1, 0, 1), inp.blocks.I, inp.blocks.K, inp.blocks.R, inp.blocks.off, inp.ntau)
+    assert e.value.code == RPA_ERR_ARG
 
 
-@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
-def test_deterministic_bitwise(precision):
-    inp = micro(**MICRO[3])
-    say("case determinism", precision)
-    a, _, ctx = gpu_chi_tau(inp, precision)
-    b, _, _ = gpu_chi_tau(inp, precision, ctx)
-    assert bool((a == b).all())
+def test_green_symmetry_check():
+    """rpa_check_green_symmetry accepts the generator's G (real and symmetric, G(-R) = G(R)^T) and
+    rejects one entry of G^occ(R) moved off its partner."""
+    import torch
+    from paper_2407_19930_amd import Context, RpaError, rpa_check_green_symmetry
+    from paper_2407_19930_amd.binding import RPA_ERR_ARG
+    inp = micro(**MICRO[1])
+    ctx = Context(0)
+    Go = torch.from_numpy(inp.Gocc).cuda()
+    Gu = torch.from_numpy(inp.Gun).cuda()
+    dev = rpa_check_green_symmetry(ctx, inp.cell.mesh, Go, Gu, 1e-12)
+    say("case G symmetry: rel dev %.3g" % dev)
+    assert dev <= 1e-13
+    Go[inp.ntau - 1, 1, 0, 1] += 1e-6 * float(Go.abs().max())
+    with pytest.raises(RpaError) as e:
+        rpa_check_green_symmetry(ctx, inp.cell.mesh, Go, Gu, 1e-12)
+    assert e.value.code == RPA_ERR_ARG
+    assert rpa_check_green_symmetry(ctx, inp.cell.mesh, Go, Gu, 1e-3) > 1e-8
+
+
+def test_context_dropped_before_plan_and_batch():
+    """A context, two plans, a batch and a session of it left in one reference cycle and collected
+    by the garbage collector, which finalises them in an order of its own (the context may go
+    first): every finaliser either destroys its object while the context lives or, once the
+    context is closed, does nothing; the process carries on and builds chi as before."""
+    import gc
+    import torch
+    from paper_2407_19930_amd import Context, Session
+    from paper_2407_19930_amd.batching import make_batch
+    from tests._gpu import batch_cell, make_plan
+    inp = micro(**MICRO[1])
+    ref, _, _ = gpu_chi_tau(inp, "fp64")
+    ref = ref.cpu().numpy()
+
+    def garbage():
+        ctx = Context(0)
+        plans = [make_plan(ctx, inp, p) for p in ("fp64", "bf16x3")]
+        batch, bplans, _ = make_batch(ctx, [batch_cell(inp)], 1, "fp32")
+        sess = Session(ctx)
+        batch.run()
+        torch.cuda.synchronize()
+        ctx.cycle = [ctx, plans, batch, bplans, sess]
+
+    for _ in range(3):
+        garbage()
+        gc.collect()
+    a, _, _ = gpu_chi_tau(inp, "fp64")
+    assert np.array_equal(a.cpu().numpy(), ref)

@@ -16,7 +16,9 @@ pytestmark = pytest.mark.gpu
 
 CHI_TOL = {"fp64": 1e-11, "fp32": 1e-5, "bf16x3": 1e-5}
 CASES = {"tiny": lambda: cfg(0),
-         "ragged": lambda: micro(seed=2, natoms=3, nao=(2, 5, 3), naux=(3, 6, 2), mesh=(3, 1, 2))}
+         "ragged": lambda: micro(seed=2, natoms=3, nao=(2, 5, 3), naux=(3, 6, 2), mesh=(3, 1, 2)),
+         # 128 ABF on one atom: both halves of the 4-wave single launch carry columns
+         "wide": lambda: micro(seed=8, natoms=2, nao=(32, 1), naux=(128, 1), mesh=(2, 1, 1), rcut=3.5, edge=4.0)}
 
 
 def say(*a):
@@ -124,11 +126,56 @@ def test_set_tuning_rejects_out_of_range(cases):
         with pytest.raises(RpaError) as e:
             plan.set_tuning(*bad)
         assert e.value.code == RPA_ERR_ARG
+    with pytest.raises(RpaError) as e:
+        plan.set_tuning(0, 16, 0, 1)         # the single fused launch is a split-BF16 variant
+    assert e.value.code == RPA_ERR_ARG
     t = plan.tuning
     assert (t.nstage_order, t.nstage_kstep, t.fused_order) == (1, 32, 1)
     pb = make_plan(ctx, inp, "bf16x3")
     with pytest.raises(RpaError):
         pb.set_tuning(0, 16, 0)             # the split-BF16 N stage has no K-step choice
     pb.set_tuning(1, 0, 1)
+    pb.set_tuning(0, 0, 0, 1)
+    for bad in (0, inp.ntau + 1):
+        with pytest.raises(RpaError) as e:
+            pb.set_tau_batch(bad)
+        assert e.value.code == RPA_ERR_ARG
     plan.close()
     pb.close()
+
+
+@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
+def test_tau_batch_and_single_launch(cases, case, precision):
+    """tau points per launch (rpa_plan_set_tau_batch) and the single fused launch over every
+    template class: every combination gives bitwise the chi of the default launches (each tau,
+    tile and item is computed by the same instructions, only the launches differ), with screening
+    off and on (the same kept-term counts)."""
+    import torch
+    from paper_2407_19930_amd import Context
+    inp, ref = cases[case]
+    say("case tau batch", case, precision)
+    ctx = Context(0)
+    d = device_inputs(inp)
+    for theta in (0.0, 0.05):
+        plan = make_plan(ctx, inp, precision)
+        if theta:
+            plan.set_screening(theta)
+        ws = torch.empty(max(plan.workspace_bytes, 1), dtype=torch.uint8, device="cuda")
+        base = _build(ctx, plan, inp, d, ws)
+        assert np.all(np.isfinite(base))
+        if not theta:
+            assert rel(base, ref) <= CHI_TOL[precision]
+        stats = plan.screening_stats() if theta else None
+        k0 = plan.tuning.nstage_kstep
+        for slots in sorted({1, 2, inp.ntau}):
+            grow = plan.set_tau_batch(slots)
+            ws = torch.empty(max(grow, 1), dtype=torch.uint8, device="cuda")
+            for single in ((0, 1, 2) if precision == "bf16x3" else (0,)):
+                plan.set_tuning(0, k0, 0, single)
+                chi = _build(ctx, plan, inp, d, ws)
+                say("  theta %g slots %d single %d: equal %s" % (theta, slots, single, np.array_equal(chi, base)))
+                assert np.array_equal(chi, base)
+                if theta:
+                    assert plan.screening_stats() == stats
+        plan.close()
