@@ -61,12 +61,14 @@ def parse():
     ap.add_argument("--lanes", type=int, default=8, help="concurrent lanes of the serving batch")
     ap.add_argument("--gen-workers", type=int, default=16, help="processes generating the serving cells")
     ap.add_argument("--ncells", type=int, default=64, help="serving cells used (the first n of 64)")
+    ap.add_argument("--serving-oracle-cells", type=int, default=8,
+                    help="serving cells of at most 4 atoms at Gamma checked against the FP64 oracle")
     ap.add_argument("--no-fp64-check", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tuning", default="auto",
                     help="launch variants of the chi0 kernels: 'auto' (rpa_plan_autotune before the warm-up) or "
-                         "NSTAGE_ORDER,NSTAGE_KSTEP,FUSED_ORDER[,FUSED_SINGLE] set explicitly (e.g. 0,16,0, the plan "
-                         "defaults)")
+                         "NSTAGE_ORDER,NSTAGE_KSTEP,FUSED_ORDER[,FUSED_SINGLE[,NSTAGE_BM]] set explicitly (e.g. "
+                         "0,16,0, the plan defaults)")
     ap.add_argument("--tau-batch", type=int, default=0,
                     help="tau points per N-stage / fused launch of the timed path (0: as many as keep the "
                          "per-tau workspace within --tau-batch-gib)")
@@ -133,18 +135,20 @@ def kernel_source_hash():
 
 
 def tuning_tag(tuning):
-    """NSTAGE_ORDER,NSTAGE_KSTEP,FUSED_ORDER,FUSED_SINGLE of a tuning dict (the form --tuning takes)."""
-    return "%d,%d,%d,%d" % (tuning["nstage_order"], tuning["nstage_kstep"], tuning["fused_order"],
-                            tuning.get("fused_single", 0))
+    """NSTAGE_ORDER,NSTAGE_KSTEP,FUSED_ORDER,FUSED_SINGLE,NSTAGE_BM of a tuning dict (the form
+    --tuning takes)."""
+    return "%d,%d,%d,%d,%d" % (tuning["nstage_order"], tuning["nstage_kstep"], tuning["fused_order"],
+                               tuning.get("fused_single", 0), tuning.get("nstage_bm", 128))
 
 
 def same_variant(kernel, tag_a, tag_b):
-    """Whether two tuning tags launch `kernel` alike: the N stage depends on its order and K
-    step, the fused kernel on its item order and single-launch flag."""
+    """Whether two tuning tags launch `kernel` alike: the N stage depends on its order, K step and
+    tile rows, the fused kernel on its item order and single-launch mode."""
+    d = ["0", "16", "0", "0", "128"]
     a, b = tag_a.split(","), tag_b.split(",")
-    a += ["0"] * (4 - len(a))
-    b += ["0"] * (4 - len(b))
-    return a[:2] == b[:2] if kernel == "nstage" else a[2:4] == b[2:4]
+    a += d[len(a):]
+    b += d[len(b):]
+    return (a[:2] + a[4:]) == (b[:2] + b[4:]) if kernel == "nstage" else a[2:4] == b[2:4]
 
 
 def recorded_traffic(kernel, precision, workload, tuning):
@@ -238,9 +242,11 @@ def serving_main(args):
     cells = serving_cells()[:args.ncells]
     dev = "cuda"
     t0 = time.perf_counter()
-    io, natoms, names = [], [], []
+    io, natoms, names, small = [], [], [], []
     with cf.ProcessPoolExecutor(max_workers=max(1, args.gen_workers), mp_context=mp.get_context("fork")) as ex:
         for k, inp in enumerate(ex.map(_gen_cell, cells)):
+            if inp.natoms <= 4 and inp.nR == 1:
+                small.append((k, inp))          # small enough for the FP64 oracle
             b = inp.blocks
             io.append(dict(nao=inp.nao, naux=inp.naux, mesh=inp.cell.mesh, blk_I=b.I, blk_K=b.K, blk_R=b.R,
                            blk_off=b.off, ntau=inp.ntau, spin_factor=inp.spin_factor, gamma_cos=inp.gamma_cos,
@@ -251,6 +257,7 @@ def serving_main(args):
             names.append(inp.cell.name)
             del inp
             log("cell %d/%d ready (%.0f s)" % (k + 1, len(cells), time.perf_counter() - t0))
+    small = small[:args.serving_oracle_cells]
     gen_s = time.perf_counter() - t0
     natoms = np.array(natoms)
     ctx = Context(0)
@@ -269,7 +276,7 @@ def serving_main(args):
         del b64
         torch.cuda.empty_cache()
     t0 = time.perf_counter()
-    batch, plans, lanes = make_batch(ctx, io, args.lanes, args.precision)
+    batch, plans, lanes = make_batch(ctx, io, args.lanes, args.precision, tune=args.tuning == "auto")
     torch.cuda.synchronize()
     capture_s = time.perf_counter() - t0
     log("batch of %d cells in %d lanes captured in %.1f s" % (len(io), args.lanes, capture_s))
@@ -290,6 +297,50 @@ def serving_main(args):
         extra["max_dEc_per_atom_vs_fp64"] = float(d.max())
         extra["worst_cell"] = names[int(d.argmax())]
         extra["speedup_vs_fp64"] = extra["fp64_ms_per_step"] / (dt * 1e3)
+    # the fused kernel of every cell once more, outside the graph and timed with HIP events
+    # (the graph overlaps cells, so its kernels have no per-cell durations): the roofline of the
+    # batch's dominant kernel over all cells
+    from paper_2407_19930_amd import build_chi0_tau
+    fused_ms, fused_alg = 0.0, 0.0
+    for c, p in zip(io, plans):
+        ws = torch.empty(max(p.workspace_bytes, 1), dtype=torch.uint8, device=dev)
+        chi = torch.empty(p.ntau * p.nR * p.nauxtot ** 2, dtype=torch.float64, device=dev)
+        ctx.profile(True)
+        build_chi0_tau(p, c["spin_factor"], c["G_occ"], c["G_un"], c["C"], ws, chi)
+        fused_ms += ctx.profile_read("fused")[0]
+        ctx.profile(False)
+        fused_alg += p.stage_flops(1)[0]
+        del ws, chi
+    peak = PEAK_BF16X3_FP32EQ if args.precision == "bf16x3" else PEAK_TFLOPS[args.precision]
+    ach = fused_alg / (fused_ms * 1e-3) / 1e12
+    roofline = {"bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak,
+                "traffic": None, "kernel": "fused", "launches_per_step": None,
+                "avg_launch_ms": fused_ms / len(io), "note": "sum over the cells' fused-kernel time, each cell "
+                "built once outside the graph"}
+    # per-cell E_c against the FP64 oracle on the cells small enough for it, and the oracle's
+    # time on them as the CPU baseline (same algorithmic flop count per cell)
+    cpu = None
+    if small and not args.no_cpu_baseline:
+        from oracle import chi0 as ochi
+        from oracle.pipeline import ec_from_chi_tau
+        host = host_info()
+        t1 = time.perf_counter()
+        dmax, worst, oflops = 0.0, None, 0.0
+        for k, inp in small:
+            ec_ref, _, _ = ec_from_chi_tau(inp, ochi.chi0_alg1(inp))
+            dd = abs(ec[k] - ec_ref) / inp.natoms
+            if dd >= dmax:
+                dmax, worst = dd, names[k]
+            oflops += plans[k].flops()[0]
+        tcpu = time.perf_counter() - t1
+        extra["oracle_cells"] = len(small)
+        extra["max_dEc_per_atom_vs_oracle"] = dmax
+        extra["worst_cell_vs_oracle"] = worst
+        cpu = {"value": oflops / tcpu / 1e12, "unit": "TFLOP/s", "cores": int(host["blas_threads"]),
+               "kind": "oracle", "cells_per_s": len(small) / tcpu,
+               "sample": "%d serving cells of at most 4 atoms at Gamma, whole path (Algorithm 1, transforms, "
+                         "LU log-det); %.1f s" % (len(small), tcpu), "host": host}
+        log("oracle on %d small cells: max dE_c/atom %.3g, %.1f s" % (len(small), dmax, tcpu))
     rec = {
         "metric": "chi0(R,tau) build TFLOP/s + E_c time, mixed vs FP64 at |dE_c| <= 1e-6 Ha/atom",
         "value": alg / dt / 1e12,
@@ -306,8 +357,8 @@ def serving_main(args):
         "config": {"workload": "serving: %d cells of 2-16 atoms (%d atoms), k-meshes 1/8/27, 8-16 tau, rcut 8 A, "
                                "one graph launch, %d lanes" % (len(io), int(natoms.sum()), args.lanes),
                    "ncells": len(io), "natoms_total": int(natoms.sum()), "lanes": args.lanes},
-        "roofline": None,
-        "cpu_baseline": None,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
         "cells_per_s": len(io) / dt,
         "alg_tflop_per_step": alg / 1e12,
         "capture_s": capture_s,
@@ -381,7 +432,7 @@ def main():
         chi0_R_to_q(ctx, cell.mesh, inp.kfrac, chi_w, cq)
         return rpa_correlation_energy(ctx, inp.womega, cq, vq, ws_ec)
 
-    build_kernels = ("pack_c", "pad_g", "nstage", "fused")
+    build_kernels = ("pack_c", "pad_g", "screen", "nstage", "split_n", "fused")
     ec_kernels = ("cos_transform", "r2q", "ec_stage")
 
     def read_profile(steps):
@@ -460,7 +511,7 @@ def main():
         torch.cuda.synchronize()
         ctx.profile(True)
         build_chi0_tau(plan, inp.spin_factor, Gocc, Gun, C, ws, chi_tau)
-        sb_ms = sum(ctx.profile_read(k)[0] for k in ("pack_c", "pad_g", "screen", "nstage", "fused"))
+        sb_ms = sum(ctx.profile_read(k)[0] for k in build_kernels)
         sf_ms = ctx.profile_read("fused")[0]
         ctx.profile(False)
         st = plan.screening_stats()

@@ -138,6 +138,8 @@ RPA_API int rpa_plan_stage_flops(const rpa_plan *plan, int stage, double *alg_fl
  *                  small items; 1: workgroups of 8 waves, one per item (up to 128 ABF columns
  *                  of V); 2: workgroups of 4 waves, one per half of an item's columns (an
  *                  item with at most 64 columns takes one), two workgroups per compute unit
+ *   nstage_bm    : rows of an N-stage output tile: 128 (4 waves), or 256 (8 waves, each
+ *                  staged C tile used for twice the rows; split-BF16 N stage only)
  * Every variant computes the same chi; the item order leaves it bitwise unchanged,
  * the K step changes the FP32/FP64 summation order only. */
 typedef struct {
@@ -148,6 +150,7 @@ typedef struct {
   double nstage_ms;
   double fused_ms;
   int fused_single;
+  int nstage_bm;
 } rpa_tuning;
 
 /* Autotuner: times every variant of the N-stage kernel, then of the fused kernel,
@@ -164,7 +167,8 @@ typedef struct {
 RPA_API int rpa_plan_autotune(rpa_plan *plan, double spin_factor, const double *G_occ, const double *G_un,
                               const double *C, void *workspace, size_t workspace_bytes, double *chi0_scratch,
                               rpa_tuning *out);
-/* The plan's current variants (defaults: plan orders, K step 16).  Errors: RPA_ERR_ARG. */
+/* The plan's current variants (defaults: plan orders, K step 16 (0 on the split-BF16 N stage),
+ * per-class fused launches, N-stage tiles of 128 rows).  Errors: RPA_ERR_ARG. */
 RPA_API int rpa_plan_get_tuning(const rpa_plan *plan, rpa_tuning *out);
 /* Sets the variants explicitly (from_cache and the times are ignored); values outside
  * the ranges above are rejected with RPA_ERR_ARG and leave the plan unchanged. */
@@ -210,7 +214,7 @@ RPA_API int rpa_plan_screening_stats(rpa_plan *plan, long long *out);
  * every launch of the library's kernels.  rpa_profile(ctx, 1) enables and resets,
  * rpa_profile(ctx, 0) disables.  rpa_profile_read waits for the recorded events and
  * returns the summed duration and launch count of one kernel ("pack_c", "pad_g",
- * "screen", "nstage", "fused", "cos_transform", "r2q", "ec_stage", "green").  Errors: RPA_ERR_ARG, RPA_ERR_HIP. */
+ * "screen", "nstage", "split_n", "fused", "cos_transform", "r2q", "ec_stage", "green").  Errors: RPA_ERR_ARG, RPA_ERR_HIP. */
 RPA_API int rpa_profile(rpa_ctx *ctx, int enable);
 RPA_API int rpa_profile_read(rpa_ctx *ctx, const char *kernel, double *total_ms, int *launches);
 

@@ -19,12 +19,21 @@ def _work(plan: Plan, nq: int, nomega: int) -> float:
     return plan.flops()[0] + 17.0 * nq * nomega * float(n) ** 3
 
 
-def make_batch(ctx, cells, nlanes: int, precision: str = "fp32"):
+# per-tau part of a cell's build workspace held at once (padded G and the N intermediate of
+# several tau points, rpa_plan_set_tau_batch): every lane holds one such workspace
+TAU_BATCH_LANE_BYTES = 6 << 30
+
+
+def make_batch(ctx, cells, nlanes: int, precision: str = "fp32", tune: bool = False,
+               tau_batch_bytes: int = TAU_BATCH_LANE_BYTES):
     """cells: list of dicts holding, per cell,
       host: nao, naux, mesh, blk_I, blk_K, blk_R, blk_off, ntau, spin_factor,
             gamma_cos [nomega, ntau], womega [nomega], q_frac [nq, 3]
       device (torch): G_occ, G_un, C (float64), v_q (complex128 [nq, n, n]).
-    Returns (Batch, plans, lane of each cell)."""
+    Each plan takes as many tau points per launch as keep the per-tau part of its workspace within
+    tau_batch_bytes (all of them for most serving cells), and with tune=True its launch variants
+    from rpa_plan_autotune on the cell's own inputs (cached by shape class in the context, so
+    cells of one shape are timed once).  Returns (Batch, plans, lane of each cell)."""
     import torch
     dev = "cuda"
     plans, shapes = [], []
@@ -32,6 +41,16 @@ def make_batch(ctx, cells, nlanes: int, precision: str = "fp32"):
         p = Plan(ctx, c["nao"], c["naux"], c["mesh"], c["blk_I"], c["blk_K"], c["blk_R"], c["blk_off"], c["ntau"],
                  precision)
         nomega, nq = np.asarray(c["gamma_cos"]).shape[0], np.asarray(c["q_frac"]).reshape(-1, 3).shape[0]
+        ws1 = p.workspace_bytes
+        tb = p.ntau
+        while tb > 1 and p.set_tau_batch(tb) - ws1 > tau_batch_bytes:
+            tb = max(1, tb // 2)
+        p.set_tau_batch(tb)
+        if tune:
+            ws = torch.empty(max(p.workspace_bytes, 1), dtype=torch.uint8, device=dev)
+            scratch = torch.empty(p.nR * p.nauxtot ** 2, dtype=torch.float64, device=dev)
+            p.autotune(c["spin_factor"], c["G_occ"], c["G_un"], c["C"], ws, scratch)
+            del ws, scratch
         plans.append(p)
         shapes.append((p.nauxtot, p.nR, p.ntau, nomega, nq))
     # largest first onto the least loaded lane

@@ -65,7 +65,7 @@ class Tuning(ctypes.Structure):
     """rpa_tuning: launch variants of a plan's N-stage and fused kernels."""
     _fields_ = [("nstage_order", ctypes.c_int), ("nstage_kstep", ctypes.c_int), ("fused_order", ctypes.c_int),
                 ("from_cache", ctypes.c_int), ("nstage_ms", ctypes.c_double), ("fused_ms", ctypes.c_double),
-                ("fused_single", ctypes.c_int)]
+                ("fused_single", ctypes.c_int), ("nstage_bm", ctypes.c_int)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -272,8 +272,10 @@ class Plan:
         self.ctx.check(self.ctx.lib.rpa_plan_get_tuning(self.h, ctypes.byref(t)))
         return t
 
-    def set_tuning(self, nstage_order: int, nstage_kstep: int, fused_order: int, fused_single: int = 0):
-        t = Tuning(int(nstage_order), int(nstage_kstep), int(fused_order), 0, 0.0, 0.0, int(fused_single))
+    def set_tuning(self, nstage_order: int, nstage_kstep: int, fused_order: int, fused_single: int = 0,
+                   nstage_bm: int = 128):
+        t = Tuning(int(nstage_order), int(nstage_kstep), int(fused_order), 0, 0.0, 0.0, int(fused_single),
+                   int(nstage_bm))
         self.ctx.check(self.ctx.lib.rpa_plan_set_tuning(self.h, ctypes.byref(t)))
 
     def set_tau_batch(self, ntau_per_launch: int) -> int:

@@ -7,6 +7,7 @@
 #include <mutex>
 #include <tuple>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -58,6 +59,35 @@ int fail(rpa_ctx *ctx, int code, const std::string &msg) {
   } while (0)
 
 size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+// Plan tables live in device memory.  The host-only build of the table code (RPA_HOST_TABLE_TEST,
+// compiled by the sanitizer test with address and undefined-behaviour checks on the host code)
+// keeps them in host memory instead and launches no kernel.
+#ifdef RPA_HOST_TABLE_TEST
+hipError_t table_alloc(int, void **p, size_t n) {
+  *p = std::malloc(n);
+  return *p ? hipSuccess : hipErrorOutOfMemory;
+}
+hipError_t table_upload(void *dst, const void *src, size_t n) {
+  std::memcpy(dst, src, n);
+  return hipSuccess;
+}
+void table_free(int, void *p) { std::free(p); }
+#else
+hipError_t table_alloc(int device, void **p, size_t n) {
+  hipError_t e = hipSetDevice(device);
+  return e == hipSuccess ? hipMalloc(p, n) : e;
+}
+hipError_t table_upload(void *dst, const void *src, size_t n) {
+  return hipMemcpy(dst, src, n, hipMemcpyHostToDevice);
+}
+void table_free(int device, void *p) {
+  // the tables may still be read by queued kernels of the plan
+  (void)hipSetDevice(device);
+  (void)hipDeviceSynchronize();
+  (void)hipFree(p);
+}
+#endif
 
 hipError_t scratch_setup(int device, void **out);   // device scratch of the no-allocation entry point
 
@@ -130,9 +160,11 @@ struct rpa_plan {
   std::vector<int> nslices;                     // per atom U: sum of n_K over its neighbours
   std::vector<int> rows_start;
   std::vector<int4> row_info;
-  std::vector<long long> noff;
+  std::vector<long long> noff, noffs;
   long long n_elems = 0;                        // N buffer elements per tau
+  long long ns_elems = 0;                       // split-BF16 N elements per tau (BF16X3 plans)
   std::vector<int> tileV, tileM, tileN;
+  std::vector<int> tile2V, tile2M, tile2N;     // tiles of 256 rows (split-BF16 N stage)
   std::vector<int> itemU, itemV, itemR;
   std::vector<PlanGroup> groups;
   double alg_flops = 0, exec_flops = 0;
@@ -146,8 +178,9 @@ struct rpa_plan {
   const int *dgsrc = nullptr;
   // XCD-grouped orders of the same tiles and items (items permuted within each group)
   NTiles tiles_x{};
+  NTiles tiles2{}, tiles2_x{};
   PairItems items_x{};
-  rpa_tuning tune{0, 16, 0, 0, 0.0, 0.0, 0};
+  rpa_tuning tune{0, 16, 0, 0, 0.0, 0.0, 0, 128};
   std::string shape_key;                        // autotuner cache key (without the architecture)
   // split-BF16 N stage (BF16X3 plans whose hi and lo parts of transposed G and C each fit a
   // 32-bit buffer view; other BF16X3 plans run the FP32 N stage)
@@ -163,7 +196,7 @@ struct rpa_plan {
   // workspace layout (bytes); the per-tau parts (padded G, N, transposed G, G-scale exponents)
   // are held for `slots` tau points at once, g_slot, n_slot, gt_slot bytes apart
   size_t ws_cp = 0, ws_cb = 0, ws_g = 0, ws_n = 0, ws_sc = 0, ws_gt = 0, ws_ct = 0, ws_total = 0;
-  size_t g_slot = 0, n_slot = 0, gt_slot = 0;
+  size_t g_slot = 0, n_slot = 0, gt_slot = 0, ns_slot = 0, ws_ns = 0;
   int slots = 1;                                // tau points per N-stage / fused launch
   // single fused launch of the split-BF16 path: per plan item its class code and the items in
   // order of decreasing work
@@ -181,7 +214,9 @@ struct rpa_plan {
     const PairItems &it = order ? items_x : items;
     return PairItems{it.U + g.start, it.V + g.start, it.R + g.start, g.count};
   }
-  const NTiles &ntiles(int order) const { return order ? tiles_x : tiles; }
+  const NTiles &ntiles(int order, int bm = 128) const {
+    return bm == 256 ? (order ? tiles2_x : tiles2) : (order ? tiles_x : tiles);
+  }
 };
 
 // ---- correlation energy ----
@@ -413,7 +448,10 @@ struct BuildSteps {
     GTl = (uint16_t *)(ws + p->ws_gt + align_up(p->gt_bytes));
     Cth = (uint16_t *)(ws + p->ws_ct);
     Ctl = (uint16_t *)(ws + p->ws_ct + align_up(p->ct_bytes));
+    Nsp = (uint16_t *)(ws + p->ws_ns);
   }
+  uint16_t *Nsp;
+  uint16_t *ns_at(int k) const { return (uint16_t *)((char *)Nsp + k * p->ns_slot); }
   // per-slot views
   T *gp_at(int k) const { return (T *)((char *)Gp + k * p->g_slot); }
   T *n_at(int k) const { return (T *)((char *)Nb + k * p->n_slot); }
@@ -442,13 +480,21 @@ struct BuildSteps {
   // N of the first `ns` slots (one launch on the split-BF16 path, one per slot otherwise)
   int nstage(const rpa_tuning &tu, int ns = 1) {
     Timed tm(ctx, "nstage");
-    const NTiles &tiles = p->ntiles(tu.nstage_order);
+    const NTiles &tiles = p->ntiles(tu.nstage_order, nbf ? tu.nstage_bm : 128);
     if (nbf)
-      HIP_TRY(ctx, launch_nstage_bf16(p->tb, tiles, GTh, GTl, p->gt_bytes, Cth, Ctl, p->ct_bytes, (float *)Nb, ns,
-                                      p->gt_slot / sizeof(uint16_t), p->n_slot / sizeof(float), s));
+      HIP_TRY(ctx, launch_nstage_bf16(p->tb, tiles, tu.nstage_bm, GTh, GTl, p->gt_bytes, Cth, Ctl, p->ct_bytes,
+                                      (float *)Nb, ns, p->gt_slot / sizeof(uint16_t), p->n_slot / sizeof(float), s));
     else
       for (int k = 0; k < ns; ++k)
         HIP_TRY(ctx, launch_nstage<T>(p->tb, tiles, gp_at(k), Cp, n_at(k), (size_t)p->cp_elems, tu.nstage_kstep, s));
+    return RPA_OK;
+  }
+  // the split-BF16 copy of N that the split-BF16 fused kernel's O GEMM reads
+  int split(int ns = 1) {
+    if (!bf16) return RPA_OK;
+    Timed tm(ctx, "split_n");
+    HIP_TRY(ctx, launch_split_n(p->tb, (const float *)Nb, Nsp, ns, p->n_slot / sizeof(float),
+                                p->ns_slot / sizeof(uint16_t), s));
     return RPA_OK;
   }
   // Screening bounds of tau t (when the plan screens).
@@ -483,6 +529,8 @@ struct BuildSteps {
       a.Cb = Cb;
       a.Nbuf = (const float *)Nb;
       a.n_stride = p->n_slot / sizeof(float);
+      a.Ns = Nsp;
+      a.ns_stride = p->ns_slot / sizeof(uint16_t);
       a.gexp = gexp;
       a.negs = negs;
       a.chi = chi_t;
@@ -508,8 +556,8 @@ struct BuildSteps {
         }
         if (bf16)
           HIP_TRY(ctx, launch_fused_bf16(p->tb, p->group_items(g, tu.fused_order), g.mt, fused_bf16_ks_class(g.js),
-                                         g.hc, (const float *)gp_at(k), Cb, (const float *)n_at(k), negs, gexp_at(k), sc,
-                                         chi_t + k * chistride, s));
+                                         g.hc, (const float *)gp_at(k), Cb, (const float *)n_at(k), ns_at(k), negs,
+                                         gexp_at(k), sc, chi_t + k * chistride, s));
         else
           HIP_TRY(ctx, launch_fused<T>(p->tb, p->group_items(g, tu.fused_order), g.mt, g.js, g.hc, gp_at(k), Cp,
                                        n_at(k), negs, gexp_at(k), sc, chi_t + k * chistride, s));
@@ -532,6 +580,7 @@ static int build_impl(rpa_plan *p, const double *G_occ, const double *G_un, cons
       if (rc == RPA_OK) rc = b.screen(G_occ, G_un, t0 + k, k);
     }
     if (rc == RPA_OK) rc = b.nstage(p->tune, ns);
+    if (rc == RPA_OK) rc = b.split(ns);
     if (rc == RPA_OK) rc = b.fused(p->tune, negs, chi0_tau + t0 * b.chistride, t0, ns);
   }
   p->scr_valid = rc == RPA_OK && p->theta > 0.0;
@@ -572,13 +621,14 @@ static int autotune_impl(rpa_plan *p, const double *G_occ, const double *G_un, c
   // N stage: tile order x K step (the split-BF16 N stage has no K-step choice)
   float tbest = 0.f;
   bool have = false;
-  const int ksteps[2] = {16, 32};
-  const int nk = b.nbf ? 1 : 2;
+  // N stage: tile order x K step (FP32 / FP64 N stage) or x tile rows (split-BF16 N stage)
+  const int ksteps[2] = {16, 32}, bms[2] = {128, 256};
   for (int order = 0; rc == RPA_OK && order < 2; ++order)
-    for (int ki = 0; rc == RPA_OK && ki < nk; ++ki) {
+    for (int ki = 0; rc == RPA_OK && ki < 2; ++ki) {
       rpa_tuning c = best;
       c.nstage_order = order;
       c.nstage_kstep = b.nbf ? 0 : ksteps[ki];
+      c.nstage_bm = b.nbf ? bms[ki] : 128;
       float ms = 0.f;
       rc = timed([&]() { return b.nstage(c); }, ms);
       if (rc == RPA_OK && (!have || ms < (1.f - kTuneMargin) * tbest)) {
@@ -586,11 +636,13 @@ static int autotune_impl(rpa_plan *p, const double *G_occ, const double *G_un, c
         have = true;
         best.nstage_order = c.nstage_order;
         best.nstage_kstep = c.nstage_kstep;
+        best.nstage_bm = c.nstage_bm;
         best.nstage_ms = ms;
       }
     }
   // fused kernel on the N of the chosen N stage
   if (rc == RPA_OK) rc = b.nstage(best);
+  if (rc == RPA_OK) rc = b.split();
   // fused kernel: item order of the per-class launches, then (split BF16) the single launch
   have = false;
   for (int cand = 0; rc == RPA_OK && cand < (bf16 ? 4 : 2); ++cand) {
@@ -614,8 +666,8 @@ static int autotune_impl(rpa_plan *p, const double *G_occ, const double *G_un, c
 
 // Workspace layout of a plan for p->slots tau points per launch: packed C (FP32 / FP64 N stage),
 // split-BF16 C (BF16X3 fused kernel), then per slot padded G and N, the G scale (partial maxima,
-// two exponents per slot), and for the split-BF16
-// N stage transposed G per slot (hi and lo parts) and C (hi and lo).
+// two exponents per slot), for the split-BF16 N stage transposed G per slot (hi and lo parts) and
+// C (hi and lo), and on BF16X3 plans the split-BF16 copy of N per slot.
 static void plan_layout(rpa_plan *p) {
   const size_t es = p->prec == RPA_FP64 ? 8 : 4;
   const int ns = p->slots;
@@ -630,7 +682,9 @@ static void plan_layout(rpa_plan *p) {
   p->ws_gt = align_up(p->ws_sc + 2 * kGscaleBlocks * sizeof(double) + 2 * ns * sizeof(int));
   p->gt_slot = p->nbf16 ? 2 * align_up(gtb) : 0;
   p->ws_ct = align_up(p->ws_gt + ns * p->gt_slot);
-  p->ws_total = align_up(p->ws_ct + (p->nbf16 ? 2 * align_up(ctb) : 0));
+  p->ws_ns = align_up(p->ws_ct + (p->nbf16 ? 2 * align_up(ctb) : 0));
+  p->ns_slot = align_up((size_t)p->ns_elems * 2);
+  p->ws_total = align_up(p->ws_ns + ns * p->ns_slot);
 }
 
 extern "C" {
@@ -850,6 +904,16 @@ int rpa_plan_create(rpa_ctx *ctx, const rpa_cell *cell, const rpa_lri_blocks *bl
         no += (long long)p->nao[K] * 2 * p->nao[V] * p->naux[V];
       }
   p->n_elems = no;
+  // split-BF16 copy of N: block (V, K, dR) holds [k][hi, lo][nu][2 n_V rounded up to 8]
+  p->noffs.resize(p->noff.size());
+  long long nso = 0;
+  for (int V = 0; V < na; ++V)
+    for (int K = 0; K < na; ++K)
+      for (int r = 0; r < nR; ++r) {
+        p->noffs[((size_t)V * na + K) * nR + r] = nso;
+        nso += (long long)p->nao[K] * 2 * p->naux[V] * ((2 * p->nao[V] + 7) / 8 * 8);
+      }
+  p->ns_elems = precision == RPA_BF16X3 ? nso : 0;
   // N-stage tiles
   const int M = 2 * nR * p->nbp;
   for (int V = 0; V < na; ++V) {
@@ -859,6 +923,11 @@ int rpa_plan_create(rpa_ctx *ctx, const rpa_cell *cell, const rpa_lri_blocks *bl
         p->tileV.push_back(V);
         p->tileM.push_back(m0);
         p->tileN.push_back(n0);
+        if (m0 % 256 == 0) {
+          p->tile2V.push_back(V);
+          p->tile2M.push_back(m0);
+          p->tile2N.push_back(n0);
+        }
       }
   }
   // fused items: atom pairs U <= V (Sec. 3.2 pair set), all R; grouped by the kernel's
@@ -919,13 +988,18 @@ int rpa_plan_create(rpa_ctx *ctx, const rpa_cell *cell, const rpa_lri_blocks *bl
       return fail(ctx, RPA_ERR_UNSUPPORTED, "more than 1024 LRI blocks for one atom");
     }
   // XCD-grouped copies of the tile list and of each group's items
-  std::vector<int> tileVx, tileMx, tileNx, itemUx, itemVx, itemRx;
+  std::vector<int> tileVx, tileMx, tileNx, itemUx, itemVx, itemRx, tile2Vx, tile2Mx, tile2Nx;
   {
     const std::vector<int> pt = xcd_grouped_order((int)p->tileV.size());
     for (int b : pt) {
       tileVx.push_back(p->tileV[b]);
       tileMx.push_back(p->tileM[b]);
       tileNx.push_back(p->tileN[b]);
+    }
+    for (int b : xcd_grouped_order((int)p->tile2V.size())) {
+      tile2Vx.push_back(p->tile2V[b]);
+      tile2Mx.push_back(p->tile2M[b]);
+      tile2Nx.push_back(p->tile2N[b]);
     }
     itemUx.resize(p->itemU.size());
     itemVx.resize(p->itemU.size());
@@ -989,6 +1063,7 @@ int rpa_plan_create(rpa_ctx *ctx, const rpa_cell *cell, const rpa_lri_blocks *bl
                s_nre = add(p->nbr_run_end.data(), nblk * 4),
                s_ncp = add(p->nbr_cp.data(), nblk * 8), s_rs = add(p->rows_start.data(), (na + 1) * 4),
                s_ri = add(p->row_info.data(), p->row_info.size() * 16), s_noff = add(p->noff.data(), p->noff.size() * 8),
+               s_noffs = add(p->noffs.data(), p->noffs.size() * 8),
                s_tV = add(p->tileV.data(), p->tileV.size() * 4), s_tM = add(p->tileM.data(), p->tileM.size() * 4),
                s_tN = add(p->tileN.data(), p->tileN.size() * 4), s_iU = add(p->itemU.data(), p->itemU.size() * 4),
                s_iV = add(p->itemV.data(), p->itemV.size() * 4), s_iR = add(p->itemR.data(), p->itemR.size() * 4),
@@ -1003,11 +1078,13 @@ int rpa_plan_create(rpa_ctx *ctx, const rpa_cell *cell, const rpa_lri_blocks *bl
   const size_t s_icls = add(p->item_cls.data(), p->item_cls.size() * 4),
                s_iord = add(p->item_order.data(), p->item_order.size() * 4),
                s_hord = add(p->half_order.data(), p->half_order.size() * 4);
+  const size_t s_t2V = add(p->tile2V.data(), p->tile2V.size() * 4), s_t2M = add(p->tile2M.data(), p->tile2M.size() * 4),
+               s_t2N = add(p->tile2N.data(), p->tile2N.size() * 4), s_t2Vx = add(tile2Vx.data(), tile2Vx.size() * 4),
+               s_t2Mx = add(tile2Mx.data(), tile2Mx.size() * 4), s_t2Nx = add(tile2Nx.data(), tile2Nx.size() * 4);
   const size_t s_tVx = add(tileVx.data(), tileVx.size() * 4), s_tMx = add(tileMx.data(), tileMx.size() * 4),
                s_tNx = add(tileNx.data(), tileNx.size() * 4), s_iUx = add(itemUx.data(), itemUx.size() * 4),
                s_iVx = add(itemVx.data(), itemVx.size() * 4), s_iRx = add(itemRx.data(), itemRx.size() * 4);
-  hipError_t he = hipSetDevice(ctx->device);
-  if (he == hipSuccess) he = hipMalloc(&p->dtab, tot);
+  hipError_t he = table_alloc(ctx->device, &p->dtab, tot);
   if (he != hipSuccess) {
     delete p;
     return fail(ctx, RPA_ERR_HIP, std::string("plan tables: ") + hipGetErrorString(he));
@@ -1015,9 +1092,9 @@ int rpa_plan_create(rpa_ctx *ctx, const rpa_cell *cell, const rpa_lri_blocks *bl
   std::vector<char> host(tot, 0);
   for (auto &s : secs)
     if (s.bytes) std::memcpy(host.data() + s.off, s.src, s.bytes);
-  he = hipMemcpy(p->dtab, host.data(), tot, hipMemcpyHostToDevice);
+  he = table_upload(p->dtab, host.data(), tot);
   if (he != hipSuccess) {
-    hipFree(p->dtab);
+    table_free(ctx->device, p->dtab);
     delete p;
     return fail(ctx, RPA_ERR_HIP, std::string("plan tables copy: ") + hipGetErrorString(he));
   }
@@ -1038,6 +1115,7 @@ int rpa_plan_create(rpa_ctx *ctx, const rpa_cell *cell, const rpa_lri_blocks *bl
   tb.rows_start = I32(s_rs);
   tb.row_info = (const int4 *)(d + secs[s_ri].off);
   tb.noff = I64(s_noff);
+  tb.noffs = I64(s_noffs);
   tb.cp_stride = I32(s_cst);
   tb.nslices = I32(s_nsl);
   tb.nbr_cb = I64(s_ncb);
@@ -1055,6 +1133,8 @@ int rpa_plan_create(rpa_ctx *ctx, const rpa_cell *cell, const rpa_lri_blocks *bl
   p->tiles = NTiles{I32(s_tV), I32(s_tM), I32(s_tN), (int)p->tileV.size()};
   p->items = PairItems{I32(s_iU), I32(s_iV), I32(s_iR), (int)p->itemU.size()};
   p->tiles_x = NTiles{I32(s_tVx), I32(s_tMx), I32(s_tNx), (int)tileVx.size()};
+  p->tiles2 = NTiles{I32(s_t2V), I32(s_t2M), I32(s_t2N), (int)p->tile2V.size()};
+  p->tiles2_x = NTiles{I32(s_t2Vx), I32(s_t2Mx), I32(s_t2Nx), (int)tile2Vx.size()};
   p->items_x = PairItems{I32(s_iUx), I32(s_iVx), I32(s_iRx), (int)itemUx.size()};
   p->pack = PackTables{I64(s_pin), I64(s_pout), I64(s_pcb), I64(s_pct), I32(s_pa), I32(s_pni), I32(s_pnk), I32(s_pst),
                        nblk};
@@ -1080,13 +1160,13 @@ int rpa_plan_create(rpa_ctx *ctx, const rpa_cell *cell, const rpa_lri_blocks *bl
 
 int rpa_plan_destroy(rpa_plan *p) {
   if (!p) return RPA_ERR_ARG;
-  if (p->dtab || p->dscr) {
-    // the tables may still be read by queued kernels of this plan
-    hipSetDevice(p->device);
-    hipDeviceSynchronize();
-    if (p->dtab) hipFree(p->dtab);
-    if (p->dscr) hipFree(p->dscr);
+  if (p->dscr) {
+    // the buffer may still be read by queued kernels of this plan
+    (void)hipSetDevice(p->device);
+    (void)hipDeviceSynchronize();
+    (void)hipFree(p->dscr);
   }
+  if (p->dtab) table_free(p->device, p->dtab);
   delete p;
   return RPA_OK;
 }
@@ -1186,6 +1266,7 @@ static bool tuning_valid(const rpa_plan *p, const rpa_tuning &t) {
   if (t.nstage_order != 0 && t.nstage_order != 1) return false;
   if (t.fused_order != 0 && t.fused_order != 1) return false;
   if (t.fused_single != 0 && !((t.fused_single == 1 || t.fused_single == 2) && p->prec == RPA_BF16X3)) return false;
+  if (t.nstage_bm != 128 && !(t.nstage_bm == 256 && p->nbf16)) return false;
   return p->nbf16 ? t.nstage_kstep == 0 : (t.nstage_kstep == 16 || t.nstage_kstep == 32);
 }
 
@@ -1201,8 +1282,8 @@ int rpa_plan_set_tuning(rpa_plan *p, const rpa_tuning *t) {
   if (!tuning_valid(p, *t))
     return fail(p->ctx, RPA_ERR_ARG,
                 "tuning out of range (orders 0 or 1; K step 16 or 32, 0 for the split-BF16 N stage; single fused "
-                "launch 0, or 1 or 2 on split-BF16 plans)");
-  p->tune = rpa_tuning{t->nstage_order, t->nstage_kstep, t->fused_order, 0, 0.0, 0.0, t->fused_single};
+                "launch 0, or 1 or 2 on split-BF16 plans; N-stage tile rows 128, or 256 for the split-BF16 N stage)");
+  p->tune = rpa_tuning{t->nstage_order, t->nstage_kstep, t->fused_order, 0, 0.0, 0.0, t->fused_single, t->nstage_bm};
   return RPA_OK;
 }
 
@@ -1691,5 +1772,26 @@ int rpa_batch_destroy(rpa_batch *b) {
   batch_release(b);
   return RPA_OK;
 }
+
+#ifdef RPA_HOST_TABLE_TEST
+// Entry points of the host-only table build: a context without a device, and a summary of a
+// plan's tables for the sanitizer test's consistency checks.
+rpa_ctx *rpa_test_host_ctx(void) { return new rpa_ctx(); }
+void rpa_test_host_ctx_free(rpa_ctx *ctx) { delete ctx; }
+int rpa_test_plan_summary(const rpa_plan *p, long long *out) {
+  if (!p || !out) return RPA_ERR_ARG;
+  long long sl = 0;
+  for (int a = 0; a < p->natoms; ++a) sl += p->nslices[a];
+  out[0] = (long long)p->ws_total;
+  out[1] = (long long)p->itemU.size();
+  out[2] = (long long)p->tileV.size();
+  out[3] = (long long)p->groups.size();
+  out[4] = p->n_elems;
+  out[5] = p->ns_elems;
+  out[6] = sl;
+  out[7] = (long long)p->half_order.size();
+  return RPA_OK;
+}
+#endif
 
 }  // extern "C"

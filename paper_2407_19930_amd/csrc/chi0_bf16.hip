@@ -99,7 +99,8 @@ struct FusedLds {
 template <int MT, int KS, int HC, int NW>
 __device__ __forceinline__ void fused_bf16_body(const Chi0Tables &tb, int U, int V, int R, int half,
                                                 const float *__restrict__ Gp, const __bf16 *__restrict__ Cb,
-                                                const float *__restrict__ Nbuf, double negs,
+                                                const float *__restrict__ Nbuf, const __bf16 *__restrict__ Ns,
+                                                double negs,
                                                 const int *__restrict__ gexp, const Screen &sc, int stat,
                                                 double *__restrict__ chi, const FusedLds &lds) {
   constexpr int NT = 64 * NW;            // threads of the workgroup
@@ -123,7 +124,8 @@ __device__ __forceinline__ void fused_bf16_body(const Chi0Tables &tb, int U, int
   const bool wave_active = w * 16 < aV;
   const bool nu_ok = nu < aV;
   // neighbour table (the entries whose M terms the screening keeps; all without screening)
-  const int3 kept = item_table<NT>(tb, sc, tb.nbr_cb, U, V, R, nbr_c, nbr_n, nbr_k, nbr_g, lds.pos, lds.meta);
+  const int3 kept =
+      item_table<NT>(tb, sc, tb.nbr_cb, tb.noffs, U, V, R, nbr_c, nbr_n, nbr_k, nbr_g, lds.pos, lds.meta);
   const int ne = kept.x;
   item_stats(sc, stat, kept);
 
@@ -228,17 +230,25 @@ __device__ __forceinline__ void fused_bf16_body(const Chi0Tables &tb, int U, int
       *reinterpret_cast<u4 *>(&(buf ? Cs1 : Cs0)[(c / CH) * RS + 4 * (c % CH)]) = rc[q];
     }
   };
-  // N rows (FP32): lane (nu, grp) holds j' = 32 ks + 8 grp + e; rows j' >= 2 n_V read zero
-  const size_t nstride = (size_t)2 * nV * aV;
-  const unsigned nview = wave_active ? (unsigned)(nstride * sizeof(float)) : 0u;
-  float nb0[KS * 8], nb1[KS * 8], nb2[KS * 8];
-  auto load_n = [&](const float *nrow, float *dst) {
+  // N rows, split BF16 (noffs layout [k][part][nu][JP]): lane (nu, grp) holds j' = 32 ks + 8 grp + e
+  // of each part, one 16-byte load per part and ks.  Past 2 n_V the rows read the zero padding,
+  // then the next rows (finite values that meet the zero A columns j' >= 2 n_V); past the slice
+  // the view reads zero.
+  const int JP = (2 * nV + 7) / 8 * 8;
+  const size_t nslice = (size_t)2 * aV * JP;
+  const unsigned nview = wave_active ? (unsigned)(nslice * sizeof(__bf16)) : 0u;
+  struct NRows {
+    NVec h[KS], l[KS];
+  };
+  NRows nb0, nb1, nb2;
+  auto load_n = [&](const __bf16 *nrow, NRows &dst) {
     const __amdgpu_buffer_rsrc_t r = buffer_view(nrow, nview);
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks)
-#pragma unroll
-      for (int e = 0; e < 8; ++e)
-        dst[ks * 8 + e] = buffer_load<float>(r, (unsigned)(((32 * ks + 8 * grp + e) * aV + nu) * sizeof(float)));
+    for (int ks = 0; ks < KS; ++ks) {
+      const unsigned o = (unsigned)(((size_t)nu * JP + 32 * ks + 8 * grp) * sizeof(__bf16));
+      dst.h[ks] = __builtin_bit_cast(NVec, __builtin_amdgcn_raw_buffer_load_b128(r, o, 0, 0));
+      dst.l[ks] = __builtin_bit_cast(NVec, __builtin_amdgcn_raw_buffer_load_b128(r, o + (unsigned)(aV * JP * 2), 0, 0));
+    }
   };
   // Slice order: the entries e of U's neighbourhood come in runs [g0, g1) of one atom K (its
   // periodic images R1); a run is walked NAO k outer, image inner, so that the workgroups of
@@ -272,18 +282,18 @@ __device__ __forceinline__ void fused_bf16_body(const Chi0Tables &tb, int U, int
   // N rows at the cursor into nb, and the cursor's C slice address into cnext (slice 0 again
   // once the cursor is past the end: in bounds, never used).
   const __bf16 *cnext = Cb;
-  auto load_at = [&](float *nb) {
+  auto load_at = [&](NRows &nb) {
     const bool more = e < ne;
     const int ea = more ? e : 0, ka = more ? k : 0;
     cnext = Cb + uniform(nbr_c[ea]) + (size_t)ka * sliceElems;
-    load_n(Nbuf + uniform(nbr_n[ea]) + (size_t)ka * nstride, nb);
+    load_n(Ns + uniform(nbr_n[ea]) + (size_t)ka * nslice, nb);
   };
   bool fcur = false;   // fold after the slice being computed
   u4 rc[NLD];
   // slice t: loads of slice t + 1's C (into rc) and of slice t + 2's N rows (into nbld), O GEMM and
   // chi += C O on the N rows of t (nbcur) and the C slice of t in LDS buffer cur, then rc to LDS.
   // live: t is a slice; live1: t + 1 is a slice.
-  auto slice = [&](const float *nbcur, float *nbld, int cur, bool live, bool live1) __attribute__((always_inline)) {
+  auto slice = [&](const NRows &nbcur, NRows &nbld, int cur, bool live, bool live1) __attribute__((always_inline)) {
     load_slice(cnext, rc);
     const bool f1 = live1 ? advance() : false;
     load_at(nbld);
@@ -300,16 +310,7 @@ __device__ __forceinline__ void fused_bf16_body(const Chi0Tables &tb, int U, int
         cl0[m] = *reinterpret_cast<const CVec *>(cs + 16 * m * RS + 8 * HC);
       }
       __builtin_amdgcn_sched_barrier(0);
-      NVec nh[KS], nl[KS];
-#pragma unroll
-      for (int ks = 0; ks < KS; ++ks)
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          __bf16 hi, lo;
-          split_bf16(nbcur[ks * 8 + q], hi, lo);
-          nh[ks][q] = hi;
-          nl[ks][q] = lo;
-        }
+      const NVec *nh = nbcur.h, *nl = nbcur.l;
       f4 o[HC];
 #pragma unroll
       for (int h = 0; h < HC; ++h) o[h] = Mfma<float>::zero();
@@ -399,7 +400,8 @@ template <int MT, int KS, int HC>
 __global__ __launch_bounds__(FB_THREADS) void fused_bf16_kernel(Chi0Tables tb, PairItems items,
                                                                 const float *__restrict__ Gp,
                                                                 const __bf16 *__restrict__ Cb,
-                                                                const float *__restrict__ Nbuf, double negs,
+                                                                const float *__restrict__ Nbuf,
+                                                                const __bf16 *__restrict__ Ns, double negs,
                                                                 const int *__restrict__ gexp, Screen sc,
                                                                 double *__restrict__ chi) {
   __shared__ __align__(16) unsigned Cs[2 * kMaxNaux * fb_row_stride<HC>()];
@@ -407,8 +409,8 @@ __global__ __launch_bounds__(FB_THREADS) void fused_bf16_kernel(Chi0Tables tb, P
   __shared__ int nbr_k[kMaxNbr], nbr_g[kMaxNbr], nbr_pos[kMaxNbr + 1], nbr_meta[3];
   const FusedLds lds{Cs, nbr_c, nbr_n, nbr_k, nbr_g, nbr_pos, nbr_meta};
   const int item = blockIdx.x;
-  fused_bf16_body<MT, KS, HC, 8>(tb, items.U[item], items.V[item], items.R[item], 0, Gp, Cb, Nbuf, negs, gexp, sc,
-                                 item, chi, lds);
+  fused_bf16_body<MT, KS, HC, 8>(tb, items.U[item], items.V[item], items.R[item], 0, Gp, Cb, Nbuf, Ns, negs, gexp,
+                                 sc, item, chi, lds);
 }
 
 // One launch over the work of several tau points and every template class.  Work unit u of slot
@@ -427,7 +429,8 @@ __device__ __forceinline__ void single_item(const Chi0Tables &tb, const SingleLa
                 a.stats ? a.stats + (size_t)slot * a.stats_stride : nullptr};
   }
   fused_bf16_body<MT, KS, HC, NW>(tb, a.U[item], a.V[item], a.R[item], half, a.Gp + slot * a.gp_stride,
-                                  reinterpret_cast<const __bf16 *>(a.Cb), a.Nbuf + slot * a.n_stride, a.negs,
+                                  reinterpret_cast<const __bf16 *>(a.Cb), a.Nbuf + slot * a.n_stride,
+                                  reinterpret_cast<const __bf16 *>(a.Ns) + slot * a.ns_stride, a.negs,
                                   a.gexp + 2 * slot, sc, item, a.chi + slot * a.chi_stride, lds);
 }
 
@@ -455,19 +458,20 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2, 2)))
 
 template <int MT, int KS, int HC>
 void launch_one_bf16(const Chi0Tables &tb, const PairItems &items, const float *Gp, const __bf16 *Cb,
-                     const float *Nbuf, double negs, const int *gexp, const Screen &sc, double *chi, hipStream_t s) {
+                     const float *Nbuf, const __bf16 *Ns, double negs, const int *gexp, const Screen &sc, double *chi,
+                     hipStream_t s) {
   hipLaunchKernelGGL((fused_bf16_kernel<MT, KS, HC>), dim3(items.count), dim3(FB_THREADS), 0, s, tb, items, Gp, Cb,
-                     Nbuf, negs, gexp, sc, chi);
+                     Nbuf, Ns, negs, gexp, sc, chi);
 }
 
 template <int MT>
 hipError_t launch_ks_hc(int ks, int hc, const Chi0Tables &tb, const PairItems &items, const float *Gp,
-                        const __bf16 *Cb, const float *Nbuf, double negs, const int *gexp, const Screen &sc,
-                        double *chi, hipStream_t s) {
-  if (ks == 1 && hc == 1) launch_one_bf16<MT, 1, 1>(tb, items, Gp, Cb, Nbuf, negs, gexp, sc, chi, s);
-  else if (ks == 1 && hc == 2) launch_one_bf16<MT, 1, 2>(tb, items, Gp, Cb, Nbuf, negs, gexp, sc, chi, s);
-  else if (ks == 2 && hc == 1) launch_one_bf16<MT, 2, 1>(tb, items, Gp, Cb, Nbuf, negs, gexp, sc, chi, s);
-  else if (ks == 2 && hc == 2) launch_one_bf16<MT, 2, 2>(tb, items, Gp, Cb, Nbuf, negs, gexp, sc, chi, s);
+                        const __bf16 *Cb, const float *Nbuf, const __bf16 *Ns, double negs, const int *gexp,
+                        const Screen &sc, double *chi, hipStream_t s) {
+  if (ks == 1 && hc == 1) launch_one_bf16<MT, 1, 1>(tb, items, Gp, Cb, Nbuf, Ns, negs, gexp, sc, chi, s);
+  else if (ks == 1 && hc == 2) launch_one_bf16<MT, 1, 2>(tb, items, Gp, Cb, Nbuf, Ns, negs, gexp, sc, chi, s);
+  else if (ks == 2 && hc == 1) launch_one_bf16<MT, 2, 1>(tb, items, Gp, Cb, Nbuf, Ns, negs, gexp, sc, chi, s);
+  else if (ks == 2 && hc == 2) launch_one_bf16<MT, 2, 2>(tb, items, Gp, Cb, Nbuf, Ns, negs, gexp, sc, chi, s);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }
@@ -485,19 +489,20 @@ hipError_t launch_pack_cb(const PackTables &pt, const double *C, uint16_t *Cb, l
 }
 
 hipError_t launch_fused_bf16(const Chi0Tables &tb, const PairItems &items, int mt, int ks, int hc, const float *Gp,
-                             const uint16_t *Cb, const float *Nbuf, double negs, const int *gexp, const Screen &sc,
-                             double *chi, hipStream_t s) {
+                             const uint16_t *Cb, const float *Nbuf, const uint16_t *Nsplit, double negs,
+                             const int *gexp, const Screen &sc, double *chi, hipStream_t s) {
   if (items.count == 0) return hipSuccess;
   const __bf16 *cb = reinterpret_cast<const __bf16 *>(Cb);
+  const __bf16 *Ns = reinterpret_cast<const __bf16 *>(Nsplit);
   switch (mt) {
-    case 1: return launch_ks_hc<1>(ks, hc, tb, items, Gp, cb, Nbuf, negs, gexp, sc, chi, s);
-    case 2: return launch_ks_hc<2>(ks, hc, tb, items, Gp, cb, Nbuf, negs, gexp, sc, chi, s);
-    case 3: return launch_ks_hc<3>(ks, hc, tb, items, Gp, cb, Nbuf, negs, gexp, sc, chi, s);
-    case 4: return launch_ks_hc<4>(ks, hc, tb, items, Gp, cb, Nbuf, negs, gexp, sc, chi, s);
-    case 5: return launch_ks_hc<5>(ks, hc, tb, items, Gp, cb, Nbuf, negs, gexp, sc, chi, s);
-    case 6: return launch_ks_hc<6>(ks, hc, tb, items, Gp, cb, Nbuf, negs, gexp, sc, chi, s);
-    case 7: return launch_ks_hc<7>(ks, hc, tb, items, Gp, cb, Nbuf, negs, gexp, sc, chi, s);
-    case 8: return launch_ks_hc<8>(ks, hc, tb, items, Gp, cb, Nbuf, negs, gexp, sc, chi, s);
+    case 1: return launch_ks_hc<1>(ks, hc, tb, items, Gp, cb, Nbuf, Ns, negs, gexp, sc, chi, s);
+    case 2: return launch_ks_hc<2>(ks, hc, tb, items, Gp, cb, Nbuf, Ns, negs, gexp, sc, chi, s);
+    case 3: return launch_ks_hc<3>(ks, hc, tb, items, Gp, cb, Nbuf, Ns, negs, gexp, sc, chi, s);
+    case 4: return launch_ks_hc<4>(ks, hc, tb, items, Gp, cb, Nbuf, Ns, negs, gexp, sc, chi, s);
+    case 5: return launch_ks_hc<5>(ks, hc, tb, items, Gp, cb, Nbuf, Ns, negs, gexp, sc, chi, s);
+    case 6: return launch_ks_hc<6>(ks, hc, tb, items, Gp, cb, Nbuf, Ns, negs, gexp, sc, chi, s);
+    case 7: return launch_ks_hc<7>(ks, hc, tb, items, Gp, cb, Nbuf, Ns, negs, gexp, sc, chi, s);
+    case 8: return launch_ks_hc<8>(ks, hc, tb, items, Gp, cb, Nbuf, Ns, negs, gexp, sc, chi, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -564,21 +569,24 @@ __global__ __launch_bounds__(256) void pad_gt_kernel(const double *__restrict__ 
   }
 }
 
-constexpr int NB_THREADS = 256;
 constexpr int NB_RS = 40;            // LDS row stride (bf16): 32 contraction values + 8 padding
 
 // gt_bytes, ct_bytes: bytes of one part (hi or lo), at most 2^32 - 2^16 (a masked load sits at
-// the view's end, so offset plus load size never wraps).
-__global__ __launch_bounds__(NB_THREADS) void nstage_bf16_kernel(Chi0Tables tb, NTiles tiles,
-                                                                  const __bf16 *__restrict__ GTh,
-                                                                  const __bf16 *__restrict__ GTl, unsigned gt_bytes,
-                                                                  const __bf16 *__restrict__ Cth,
-                                                                  const __bf16 *__restrict__ Ctl, unsigned ct_bytes,
-                                                                  float *__restrict__ Nbuf, size_t gt_slot,
-                                                                  size_t n_slot) {
-  // [buffer][part hi/lo][128 rows x NB_RS]
-  __shared__ __align__(16) __bf16 As[2][2][128 * NB_RS];
+// the view's end, so offset plus load size never wraps).  BM: tile rows, 128 (4 waves) or 256
+// (8 waves, each B tile then serves twice the rows); 128 columns, waves of 64 x 64.
+template <int BM>
+__global__ __launch_bounds__(2 * BM) void nstage_bf16_kernel(Chi0Tables tb, NTiles tiles,
+                                                             const __bf16 *__restrict__ GTh,
+                                                             const __bf16 *__restrict__ GTl, unsigned gt_bytes,
+                                                             const __bf16 *__restrict__ Cth,
+                                                             const __bf16 *__restrict__ Ctl, unsigned ct_bytes,
+                                                             float *__restrict__ Nbuf, size_t gt_slot,
+                                                             size_t n_slot) {
+  // [buffer][part hi/lo][rows x NB_RS]
+  __shared__ __align__(16) __bf16 As[2][2][BM * NB_RS];
   __shared__ __align__(16) __bf16 Bs[2][2][128 * NB_RS];
+  // B loader: 128 rows x 4 groups of 8 over the 2 BM threads, BG groups per thread
+  constexpr int BG = 512 / (2 * BM);
 
   const int t = blockIdx.x;
   // tau slot of the launch
@@ -608,13 +616,14 @@ __global__ __launch_bounds__(NB_THREADS) void nstage_bf16_kernel(Chi0Tables tb, 
     const int dR = rem - kk * nR;
     tb.bvk.split(dR, d0, d1, d2);
   }
-  const int n = n0 + lr;
+  const int br = BG == 2 ? lr : tid >> 2, bq0 = BG == 2 ? 2 * lh : tid & 3;   // B row, first group
+  const int n = n0 + br;
   const bool nvalid = n < NV;
   const __amdgpu_buffer_rsrc_t gvh = buffer_view(GTh, gt_bytes), gvl = buffer_view(GTl, gt_bytes);
   const __amdgpu_buffer_rsrc_t cvh = buffer_view(Cth, ct_bytes), cvl = buffer_view(Ctl, ct_bytes);
   const int n0m = tb.bvk.n0, n1m = tb.bvk.n1, n2m = tb.bvk.n2;
 
-  u4 ra[2][2], rb[2][2];                       // [group of the pair][part]
+  u4 ra[2][2], rb[BG][2];                      // [group][part]
   auto load = [&](int ks) {
     // the 4 groups of the K step: wave-uniform table reads (scalar loads)
     int4 gq[4];
@@ -634,9 +643,8 @@ __global__ __launch_bounds__(NB_THREADS) void nstage_bf16_kernel(Chi0Tables tb, 
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const int4 gr = lh ? gq[2 + q] : gq[q];
-      const long long go = lh ? oq[2 + q] : oq[q];
       const bool valid = lh ? vq[2 + q] : vq[q];
-      unsigned oa = gt_bytes, ob = ct_bytes;  // default: past the view, the load reads zero
+      unsigned oa = gt_bytes;                 // default: past the view, the load reads zero
       if (valid && mvalid) {
         int c0 = d0 - (gr.y & 1023), c1 = d1 - ((gr.y >> 10) & 1023), c2 = d2 - (gr.y >> 20);
         c0 += c0 < 0 ? n0m : 0;
@@ -645,9 +653,19 @@ __global__ __launch_bounds__(NB_THREADS) void nstage_bf16_kernel(Chi0Tables tb, 
         const int Y = (c0 * n1m + c1) * n2m + c2;
         oa = (unsigned)(((((size_t)ss * nR + Y) * nbp + kk) * nbq + gr.x) * sizeof(__bf16));
       }
-      if (valid && nvalid) ob = (unsigned)((go + (size_t)n * gr.z) * sizeof(__bf16));
       ra[q][0] = __builtin_bit_cast(u4, __builtin_amdgcn_raw_buffer_load_b128(gvh, oa, 0, 0));
       ra[q][1] = __builtin_bit_cast(u4, __builtin_amdgcn_raw_buffer_load_b128(gvl, oa, 0, 0));
+    }
+#pragma unroll
+    for (int q = 0; q < BG; ++q) {
+      // group bq0 + q of the K step, chosen by selects (a per-lane index into the group arrays
+      // would put them in scratch memory)
+      const int bq = bq0 + q;
+      const bool vb = bq == 0 ? vq[0] : bq == 1 ? vq[1] : bq == 2 ? vq[2] : vq[3];
+      const long long obq = bq == 0 ? oq[0] : bq == 1 ? oq[1] : bq == 2 ? oq[2] : oq[3];
+      const int zb = bq == 0 ? gq[0].z : bq == 1 ? gq[1].z : bq == 2 ? gq[2].z : gq[3].z;
+      unsigned ob = ct_bytes;
+      if (vb && nvalid) ob = (unsigned)((obq + (size_t)n * zb) * sizeof(__bf16));
       rb[q][0] = __builtin_bit_cast(u4, __builtin_amdgcn_raw_buffer_load_b128(cvh, ob, 0, 0));
       rb[q][1] = __builtin_bit_cast(u4, __builtin_amdgcn_raw_buffer_load_b128(cvl, ob, 0, 0));
     }
@@ -656,11 +674,13 @@ __global__ __launch_bounds__(NB_THREADS) void nstage_bf16_kernel(Chi0Tables tb, 
 #pragma unroll
     for (int q = 0; q < 2; ++q)
 #pragma unroll
-      for (int p = 0; p < 2; ++p) {
-        const int off = lr * NB_RS + 8 * (2 * lh + q);
-        *reinterpret_cast<u4 *>(&As[buf][p][off]) = ra[q][p];
-        *reinterpret_cast<u4 *>(&Bs[buf][p][off]) = rb[q][p];
-      }
+      for (int p = 0; p < 2; ++p)
+        *reinterpret_cast<u4 *>(&As[buf][p][lr * NB_RS + 8 * (2 * lh + q)]) = ra[q][p];
+#pragma unroll
+    for (int q = 0; q < BG; ++q)
+#pragma unroll
+      for (int p = 0; p < 2; ++p)
+        *reinterpret_cast<u4 *>(&Bs[buf][p][br * NB_RS + 8 * (bq0 + q)]) = rb[q][p];
   };
 
   f4 acc[4][4];
@@ -728,6 +748,55 @@ __global__ __launch_bounds__(NB_THREADS) void nstage_bf16_kernel(Chi0Tables tb, 
 
 }  // namespace
 
+namespace {
+
+// Split-BF16 copy of N for the fused kernel's O GEMM: workgroup (x, y) = (block (V, K, dR), slot);
+// each thread unit (k, 8 rows j', nu) reads 8 FP32 values N[k][s][j][nu] (j' = s n_V + j, zero
+// past 2 n_V) and writes their hi and lo parts as one 16-byte store each at [k][part][nu][j'].
+__global__ __launch_bounds__(256) void split_n_kernel(Chi0Tables tb, const float *__restrict__ N,
+                                                      __bf16 *__restrict__ Ns, size_t n_slot, size_t ns_slot) {
+  const int blk = blockIdx.x;
+  const int nR = tb.nR, na = tb.natoms;
+  const int vk = blk / nR, K = vk % na, V = vk / na;
+  const int nK = tb.nao[K], nV = tb.nao[V], aV = tb.naux[V];
+  const int JP = (2 * nV + 7) / 8 * 8, NO = JP / 8;
+  const float *src = N + (size_t)blockIdx.y * n_slot + tb.noff[blk];
+  __bf16 *dst = Ns + (size_t)blockIdx.y * ns_slot + tb.noffs[blk];
+  const int units = nK * NO * aV;
+  for (int u = threadIdx.x; u < units; u += blockDim.x) {
+    const int nu = u % aV, r = u / aV;
+    const int o = r % NO, k = r / NO;
+    bf8 hi, lo;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int jp = 8 * o + e;
+      float x = 0.f;
+      if (jp < 2 * nV) {
+        const int sch = jp >= nV, j = jp - sch * nV;
+        x = src[((size_t)(k * 2 + sch) * nV + j) * aV + nu];
+      }
+      __bf16 h, l;
+      split_bf16(x, h, l);
+      hi[e] = h;
+      lo[e] = l;
+    }
+    *reinterpret_cast<bf8 *>(dst + ((size_t)(k * 2) * aV + nu) * JP + 8 * o) = hi;
+    *reinterpret_cast<bf8 *>(dst + ((size_t)(k * 2 + 1) * aV + nu) * JP + 8 * o) = lo;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_split_n(const Chi0Tables &tb, const float *N, uint16_t *Ns, int nslots, size_t n_slot, size_t ns_slot,
+                          hipStream_t s) {
+  const long long nblk = (long long)tb.natoms * tb.natoms * tb.nR;
+  if (nblk == 0 || nslots <= 0) return hipSuccess;
+  if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(split_n_kernel, dim3((unsigned)nblk, nslots), dim3(256), 0, s, tb, N,
+                     reinterpret_cast<__bf16 *>(Ns), n_slot, ns_slot);
+  return hipGetLastError();
+}
+
 hipError_t launch_pack_ctn(const PackTables &pt, const double *C, uint16_t *Cth, uint16_t *Ctl, long long maxblk,
                            hipStream_t s) {
   if (pt.nblk == 0) return hipSuccess;
@@ -747,14 +816,21 @@ hipError_t launch_pad_gt(const double *Gocc, const double *Gun, int nR, int nb, 
   return hipGetLastError();
 }
 
-hipError_t launch_nstage_bf16(const Chi0Tables &tb, const NTiles &tiles, const uint16_t *GTh, const uint16_t *GTl,
-                              unsigned gt_bytes, const uint16_t *Cth, const uint16_t *Ctl, unsigned ct_bytes,
-                              float *Nbuf, int nslots, size_t gt_slot, size_t n_slot, hipStream_t s) {
+hipError_t launch_nstage_bf16(const Chi0Tables &tb, const NTiles &tiles, int bm, const uint16_t *GTh,
+                              const uint16_t *GTl, unsigned gt_bytes, const uint16_t *Cth, const uint16_t *Ctl,
+                              unsigned ct_bytes, float *Nbuf, int nslots, size_t gt_slot, size_t n_slot,
+                              hipStream_t s) {
   if (tiles.count == 0 || nslots <= 0) return hipSuccess;
-  hipLaunchKernelGGL(nstage_bf16_kernel, dim3(tiles.count, nslots), dim3(NB_THREADS), 0, s, tb, tiles,
-                     reinterpret_cast<const __bf16 *>(GTh), reinterpret_cast<const __bf16 *>(GTl), gt_bytes,
-                     reinterpret_cast<const __bf16 *>(Cth), reinterpret_cast<const __bf16 *>(Ctl), ct_bytes, Nbuf,
-                     gt_slot, n_slot);
+  const __bf16 *gh = reinterpret_cast<const __bf16 *>(GTh), *gl = reinterpret_cast<const __bf16 *>(GTl);
+  const __bf16 *ch = reinterpret_cast<const __bf16 *>(Cth), *cl = reinterpret_cast<const __bf16 *>(Ctl);
+  if (bm == 256)
+    hipLaunchKernelGGL(nstage_bf16_kernel<256>, dim3(tiles.count, nslots), dim3(512), 0, s, tb, tiles, gh, gl,
+                       gt_bytes, ch, cl, ct_bytes, Nbuf, gt_slot, n_slot);
+  else if (bm == 128)
+    hipLaunchKernelGGL(nstage_bf16_kernel<128>, dim3(tiles.count, nslots), dim3(256), 0, s, tb, tiles, gh, gl,
+                       gt_bytes, ch, cl, ct_bytes, Nbuf, gt_slot, n_slot);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

@@ -30,6 +30,10 @@ struct Chi0Tables {
   const int4 *row_info;
   // N buffer: block (V, K, dR) at noff[(V * natoms + K) * nR + dR], layout [k][s][j][nu]
   const long long *noff;
+  // split-BF16 copy of N for the O GEMM of the split-BF16 fused kernel: block (V, K, dR) at
+  // noffs[...] (bf16 elements), layout [k][part hi/lo][nu][JP], JP = 2 n_V rounded up to 8, zeros
+  // in the j' >= 2 n_V padding
+  const long long *noffs;
   const int *cp_stride;                       // [natoms] packed row stride of atom U's blocks
   int natoms, nb, nbp, nauxtot, nR;           // nbp: nb rounded up to a multiple of 8
   Bvk bvk;
@@ -102,13 +106,18 @@ hipError_t launch_pack_ctn(const PackTables &pt, const double *C, uint16_t *Cth,
 hipError_t launch_pad_gt(const double *Gocc, const double *Gun, int nR, int nb, int nbp, int nbq, const int *gsrc,
                          const int *gexp, uint16_t *GTh, uint16_t *GTl, hipStream_t s);
 // nslots tau points in one launch (grid.y): slot t reads GTh/GTl + t gt_slot (elements) and
-// writes Nbuf + t n_slot (elements).
-hipError_t launch_nstage_bf16(const Chi0Tables &tb, const NTiles &tiles, const uint16_t *GTh, const uint16_t *GTl,
-                              unsigned gt_bytes, const uint16_t *Cth, const uint16_t *Ctl, unsigned ct_bytes,
-                              float *Nbuf, int nslots, size_t gt_slot, size_t n_slot, hipStream_t s);
+// writes Nbuf + t n_slot (elements).  bm: tile rows, 128 or 256 (tiles listed for that height).
+hipError_t launch_nstage_bf16(const Chi0Tables &tb, const NTiles &tiles, int bm, const uint16_t *GTh,
+                              const uint16_t *GTl, unsigned gt_bytes, const uint16_t *Cth, const uint16_t *Ctl,
+                              unsigned ct_bytes, float *Nbuf, int nslots, size_t gt_slot, size_t n_slot,
+                              hipStream_t s);
 hipError_t launch_fused_bf16(const Chi0Tables &tb, const PairItems &items, int mt, int ks, int hc, const float *Gp,
-                             const uint16_t *Cb, const float *Nbuf, double negs, const int *gexp, const Screen &sc,
-                             double *chi, hipStream_t s);
+                             const uint16_t *Cb, const float *Nbuf, const uint16_t *Ns, double negs, const int *gexp,
+                             const Screen &sc, double *chi, hipStream_t s);
+// Split-BF16 copy Ns (noffs layout, hi and lo parts) of the FP32 N intermediate of nslots tau
+// points (slot t at N + t n_slot and Ns + t ns_slot, elements).
+hipError_t launch_split_n(const Chi0Tables &tb, const float *N, uint16_t *Ns, int nslots, size_t n_slot, size_t ns_slot,
+                          hipStream_t s);
 
 // Single split-BF16 fused launch over the items of nslots tau points, every template class in one
 // launch (chi0_bf16.hip).  Per slot (tau of the launch): Gp, N, the two G-scale exponents, chi,
@@ -123,6 +132,8 @@ struct SingleLaunch {
   const uint16_t *Cb;
   const float *Nbuf;
   size_t n_stride;
+  const uint16_t *Ns;                // split-BF16 N (noffs layout)
+  size_t ns_stride;
   const int *gexp;                   // [nslots][2]
   double negs;
   double *chi;

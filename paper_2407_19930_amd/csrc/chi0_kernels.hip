@@ -402,7 +402,8 @@ __global__ __launch_bounds__(FU_THREADS) void fused_kernel(Chi0Tables tb, PairIt
   const int hc = HC;                          // i-tiles of U (nU <= 16 HC)
   // neighbour table of this item (the entries whose M terms the screening keeps; all without
   // screening) and zeroed C buffers
-  const int3 kept = item_table<FU_THREADS>(tb, sc, tb.nbr_cp, U, V, R, nbr_c, nbr_n, nbr_k, nbr_g, nbr_pos, nbr_meta);
+  const int3 kept =
+      item_table<FU_THREADS>(tb, sc, tb.nbr_cp, tb.noff, U, V, R, nbr_c, nbr_n, nbr_k, nbr_g, nbr_pos, nbr_meta);
   const int ne = kept.x;
   item_stats(sc, blockIdx.x, kept);
   for (int e = tid; e < 2 * kMaxNaux * IP + 4; e += FU_THREADS) Cs[e] = T(0);

@@ -6,7 +6,7 @@
 
 // Fills the LDS tables of item (U, V, R) with one row per kept entry e of the neighbourhood N[U]
 // (Algorithm 1's loop over K(R1)): nbr_k = NAO count of K, nbr_c = cofs[e] (offset of the C block
-// in the kernel's packed layout), nbr_n = offset of the N block (V, K, R1 - R), nbr_g = end of the
+// in the kernel's packed layout), nbr_n = nofs of the N block (V, K, R1 - R), nbr_g = end of the
 // run of kept entries with the same atom K.  Without screening every entry is kept.  With
 // screening the M terms of entry e are kept when gb(U, V, R) gn(V, K, R1 - R) >= cut, and the
 // kept entries keep their order, so each atom's run stays contiguous.  pos: LDS scratch of
@@ -15,8 +15,8 @@
 // kept, Z terms kept} (wave-uniform).
 template <int NT>
 __device__ __forceinline__ int3 item_table(const Chi0Tables &tb, const Screen &sc, const long long *__restrict__ cofs,
-                                           int U, int V, int R, long long *nbr_c, long long *nbr_n, int *nbr_k,
-                                           int *nbr_g, int *pos, int *meta) {
+                                           const long long *__restrict__ nofs, int U, int V, int R, long long *nbr_c,
+                                           long long *nbr_n, int *nbr_k, int *nbr_g, int *pos, int *meta) {
   const int tid = threadIdx.x;
   const int natoms = tb.natoms, nR = tb.nR;
   const int e0 = tb.nbr_start[U], ne = tb.nbr_start[U + 1] - e0;
@@ -25,7 +25,7 @@ __device__ __forceinline__ int3 item_table(const Chi0Tables &tb, const Screen &s
       const int K = tb.nbr_K[e0 + e];
       nbr_k[e] = tb.nao[K];
       nbr_c[e] = cofs[e0 + e];
-      nbr_n[e] = tb.noff[((size_t)V * natoms + K) * nR + tb.bvk.sub(tb.nbr_R1[e0 + e], R)];
+      nbr_n[e] = nofs[((size_t)V * natoms + K) * nR + tb.bvk.sub(tb.nbr_R1[e0 + e], R)];
       nbr_g[e] = tb.nbr_run_end[e0 + e] - e0;
     }
     return make_int3(ne, tb.nslices[U], 1);
@@ -65,7 +65,7 @@ __device__ __forceinline__ int3 item_table(const Chi0Tables &tb, const Screen &s
       const int K = tb.nbr_K[e0 + e];
       nbr_k[p] = tb.nao[K];
       nbr_c[p] = cofs[e0 + e];
-      nbr_n[p] = tb.noff[((size_t)V * natoms + K) * nR + tb.bvk.sub(tb.nbr_R1[e0 + e], R)];
+      nbr_n[p] = nofs[((size_t)V * natoms + K) * nR + tb.bvk.sub(tb.nbr_R1[e0 + e], R)];
       nbr_g[p] = pos[tb.nbr_run_end[e0 + e] - e0];
     }
   }

@@ -60,19 +60,21 @@ def test_every_variant_computes_the_same_chi(cases, case, precision):
     ksteps = [0] if t0.nstage_kstep == 0 else [16, 32]
     assert t0.nstage_kstep in (0, 16)
     base = {}
+    bms = (128, 256) if precision == "bf16x3" else (128,)
     for k in ksteps:
-        for no in (0, 1):
-            for fo in (0, 1):
-                plan.set_tuning(no, k, fo)
-                chi = _build(ctx, plan, inp, d, ws)
-                e = rel(chi, ref)
-                say("  kstep %d nstage_order %d fused_order %d: rel err %.3g" % (k, no, fo, e))
-                assert np.all(np.isfinite(chi))
-                assert e <= CHI_TOL[precision]
-                if k not in base:
-                    base[k] = chi
-                else:
-                    assert np.array_equal(chi, base[k])     # orders: bitwise the same chi
+        for bm in bms:
+            for no in (0, 1):
+                for fo in (0, 1):
+                    plan.set_tuning(no, k, fo, 0, bm)
+                    chi = _build(ctx, plan, inp, d, ws)
+                    e = rel(chi, ref)
+                    say("  kstep %d bm %d nstage_order %d fused_order %d: rel err %.3g" % (k, bm, no, fo, e))
+                    assert np.all(np.isfinite(chi))
+                    assert e <= CHI_TOL[precision]
+                    if k not in base:
+                        base[k] = chi
+                    else:
+                        assert np.array_equal(chi, base[k])     # orders, tile rows: bitwise the same chi
     plan.close()
 
 
@@ -122,7 +124,7 @@ def test_set_tuning_rejects_out_of_range(cases):
     ctx = Context(0)
     plan = make_plan(ctx, inp, "fp32")
     plan.set_tuning(1, 32, 1)
-    for bad in ((2, 16, 0), (0, 24, 0), (0, 16, -1), (0, 0, 0)):
+    for bad in ((2, 16, 0), (0, 24, 0), (0, 16, -1), (0, 0, 0), (0, 16, 0, 0, 256)):
         with pytest.raises(RpaError) as e:
             plan.set_tuning(*bad)
         assert e.value.code == RPA_ERR_ARG
