@@ -36,7 +36,7 @@ PEAK_BF16X3_FP32EQ = 2500.0 / 3.0
 # sources of the chi0 kernels; the HBM traffic recorded under profiles/ is used only while
 # their hash matches the one the counters were taken with
 KERNEL_SOURCES = ("paper_2407_19930_amd/csrc/chi0_kernels.hip", "paper_2407_19930_amd/csrc/chi0_bf16.hip",
-                  "paper_2407_19930_amd/csrc/chi0_kernels.h",
+                  "paper_2407_19930_amd/csrc/chi0_kernels.h", "paper_2407_19930_amd/csrc/item_table.h",
                   "paper_2407_19930_amd/csrc/common.h")
 
 
@@ -152,10 +152,10 @@ def same_variant(kernel, tag_a, tag_b):
 
 
 def recorded_traffic(kernel, precision, workload, tuning):
-    """HBM bytes per launch from the committed counter summary, or None when there is none for
-    this kernel/precision/workload and launch variant, or the kernel sources changed since it
-    was taken.  The summary holds lines
-    `traffic <kernel> <precision> <workload> <bytes per launch> <hash> <tuning>`."""
+    """HBM bytes per tau point from the committed counter summary (the bench multiplies them by
+    the tau points of one launch), or None when there is none for this kernel/precision/workload
+    and launch variant, or the kernel sources changed since it was taken.  The summary holds lines
+    `traffic <kernel> <precision> <workload> <bytes per tau> <hash> <tuning>`."""
     path = os.path.join(ROOT, "profiles", "pmc_%s_%s_%s.md" % (kernel, workload, precision))
     if not os.path.exists(path):
         return None
@@ -369,6 +369,26 @@ def serving_main(args):
     print(json.dumps(rec))
 
 
+def ec_stage_rate(n, q_frac, nomega, kt, steps):
+    """FP64 rate of the energy stage (complex GEMMs and Cholesky factorisations, against the
+    78.6 TFLOP/s FP64 MFMA peak).  Per (q, omega): T = chi L with L lower triangular (n^3 / 2
+    complex multiply-adds, 4 n^3 flops), B = L^H T on the lower triangle (n^3 / 6 complex
+    multiply-adds, 4 n^3 / 3 flops), the Cholesky of I - B (n^3 / 3 complex multiply-adds,
+    8 n^3 / 3 flops): 8 n^3; per q the Cholesky of v(q), 8 n^3 / 3.  `model` counts every q as
+    complex; `executed` counts the q points whose chi(q) is real (time-reversal invariant q: every
+    fractional component 0 or 1/2) with T at two real products per complex one (2 n^3 flops)."""
+    q = np.asarray(q_frac).reshape(-1, 3)
+    nq = len(q)
+    real = int(np.sum(np.all(np.isclose(np.mod(2.0 * q, 1.0), 0.0) | np.isclose(np.mod(2.0 * q, 1.0), 1.0), axis=1)))
+    n3 = float(n) ** 3
+    model = nq * nomega * 8.0 * n3 + nq * 8.0 / 3.0 * n3
+    executed = model - real * nomega * 2.0 * n3
+    ms = kt["ec_stage"][0] / steps
+    return {"ms": ms, "model_tflop": model / 1e12, "executed_tflop": executed / 1e12, "real_q": real, "nq": nq,
+            "model_tflops": model / (ms * 1e-3) / 1e12, "executed_tflops": executed / (ms * 1e-3) / 1e12,
+            "executed_frac_fp64_peak": executed / (ms * 1e-3) / 1e12 / PEAK_TFLOPS["fp64"]}
+
+
 def gate(chi_err, dEc):
     """Accuracy bars of the mixed path against the FP64 path on the same inputs."""
     return {"chi_rel_err_vs_fp64": chi_err, "dEc_per_atom_vs_fp64": dEc, "chi_bar": 1e-5, "dEc_bar": 1e-6,
@@ -553,8 +573,9 @@ def main():
         peak = PEAK_BF16X3_FP32EQ if (dom == "fused" or split_n) else PEAK_TFLOPS["fp32"]
     else:
         peak = PEAK_TFLOPS[args.precision]
+    tr = recorded_traffic(dom, args.precision, cell.name, tuning)
     roofline = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                "traffic": recorded_traffic(dom, args.precision, cell.name, tuning), "kernel": dom,
+                "traffic": tr * nt / launches_per_step if tr is not None else None, "kernel": dom,
                 "launches_per_step": launches_per_step, "avg_launch_ms": avg_ms,
                 "executed_achieved": executed, "executed_frac": executed / peak,
                 "mfma_busy": recorded_counters(dom, args.precision, cell.name)}
@@ -601,6 +622,7 @@ def main():
         "build_ms": build_ms,
         "build_tflops": alg_flops / (build_ms * 1e-3) / 1e12,
         "ec_time_ms": ec_ms,
+        "ec_stage": ec_stage_rate(N, inp.kfrac, len(inp.omega), kt, args.steps),
         "kernel_ms": {k: v[0] / args.steps for k, v in kt.items()},
         "Ec_per_atom": ec / inp.natoms,
     }

@@ -290,10 +290,28 @@ __device__ __forceinline__ void fused_bf16_body(const Chi0Tables &tb, int U, int
   };
   bool fcur = false;   // fold after the slice being computed
   u4 rc[NLD];
-  // slice t: loads of slice t + 1's C (into rc) and of slice t + 2's N rows (into nbld), O GEMM and
-  // chi += C O on the N rows of t (nbcur) and the C slice of t in LDS buffer cur, then rc to LDS.
-  // live: t is a slice; live1: t + 1 is a slice.
-  auto slice = [&](const NRows &nbcur, NRows &nbld, int cur, bool live, bool live1) __attribute__((always_inline)) {
+  // O of a slice, A [G^un | G^occ](R) times the slice's split N rows (3 products)
+  auto ogemm = [&](const NRows &nb, f4 *o) __attribute__((always_inline)) {
+#pragma unroll
+    for (int h = 0; h < HC; ++h) o[h] = Mfma<float>::zero();
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+      for (int h = 0; h < HC; ++h) {
+        o[h] = BfMfma<8>::fma(ah[h][ks], nb.h[ks], o[h]);
+        o[h] = BfMfma<8>::fma(ah[h][ks], nb.l[ks], o[h]);
+        o[h] = BfMfma<8>::fma(al[h][ks], nb.h[ks], o[h]);
+      }
+  };
+  // The O GEMM runs one slice ahead of chi += C O: slice t takes O(t) from the slice before and
+  // issues O(t + 1) on the MFMAs while O(t) is split into its bf16 parts, so the split does not
+  // wait for its own GEMM.
+  f4 onext[HC];
+  // slice t: loads of slice t + 1's C (into rc) and of slice t + 2's N rows (into nbld), O GEMM of
+  // t + 1 (N rows nbnext), chi += C O(t) with the C slice of t in LDS buffer cur, then rc to LDS.
+  // live: t is a slice; live1: t + 1 is a slice.  Past the last slice the cursor reads slice 0
+  // again, so every O GEMM sees finite rows.
+  auto slice = [&](const NRows &nbnext, NRows &nbld, int cur, bool live, bool live1) __attribute__((always_inline)) {
     load_slice(cnext, rc);
     const bool f1 = live1 ? advance() : false;
     load_at(nbld);
@@ -310,18 +328,10 @@ __device__ __forceinline__ void fused_bf16_body(const Chi0Tables &tb, int U, int
         cl0[m] = *reinterpret_cast<const CVec *>(cs + 16 * m * RS + 8 * HC);
       }
       __builtin_amdgcn_sched_barrier(0);
-      const NVec *nh = nbcur.h, *nl = nbcur.l;
       f4 o[HC];
 #pragma unroll
-      for (int h = 0; h < HC; ++h) o[h] = Mfma<float>::zero();
-#pragma unroll
-      for (int ks = 0; ks < KS; ++ks)
-#pragma unroll
-        for (int h = 0; h < HC; ++h) {
-          o[h] = BfMfma<8>::fma(ah[h][ks], nh[ks], o[h]);
-          o[h] = BfMfma<8>::fma(ah[h][ks], nl[ks], o[h]);
-          o[h] = BfMfma<8>::fma(al[h][ks], nh[ks], o[h]);
-        }
+      for (int h = 0; h < HC; ++h) o[h] = onext[h];
+      ogemm(nbnext, onext);
       CVec bh, bl;
 #pragma unroll
       for (int h = 0; h < HC; ++h)
@@ -366,13 +376,14 @@ __device__ __forceinline__ void fused_bf16_body(const Chi0Tables &tb, int U, int
     fcur = advance();
     load_at(nb1);
     __syncthreads();
+    ogemm(nb0, onext);
     for (int t = 0; t < nsl; t += 6) {
-      slice(nb0, nb2, 0, true, t + 1 < nsl);
-      slice(nb1, nb0, 1, t + 1 < nsl, t + 2 < nsl);
-      slice(nb2, nb1, 0, t + 2 < nsl, t + 3 < nsl);
-      slice(nb0, nb2, 1, t + 3 < nsl, t + 4 < nsl);
-      slice(nb1, nb0, 0, t + 4 < nsl, t + 5 < nsl);
-      slice(nb2, nb1, 1, t + 5 < nsl, t + 6 < nsl);
+      slice(nb1, nb2, 0, true, t + 1 < nsl);
+      slice(nb2, nb0, 1, t + 1 < nsl, t + 2 < nsl);
+      slice(nb0, nb1, 0, t + 2 < nsl, t + 3 < nsl);
+      slice(nb1, nb2, 1, t + 3 < nsl, t + 4 < nsl);
+      slice(nb2, nb0, 0, t + 4 < nsl, t + 5 < nsl);
+      slice(nb0, nb1, 1, t + 5 < nsl, t + 6 < nsl);
     }
   }
 
@@ -750,49 +761,58 @@ __global__ __launch_bounds__(2 * BM) void nstage_bf16_kernel(Chi0Tables tb, NTil
 
 namespace {
 
-// Split-BF16 copy of N for the fused kernel's O GEMM: workgroup (x, y) = (block (V, K, dR), slot);
-// each thread unit (k, 8 rows j', nu) reads 8 FP32 values N[k][s][j][nu] (j' = s n_V + j, zero
-// past 2 n_V) and writes their hi and lo parts as one 16-byte store each at [k][part][nu][j'].
-__global__ __launch_bounds__(256) void split_n_kernel(Chi0Tables tb, const float *__restrict__ N,
-                                                      __bf16 *__restrict__ Ns, size_t n_slot, size_t ns_slot) {
-  const int blk = blockIdx.x;
+// Split-BF16 copy of N for the fused kernel's O GEMM: workgroup (x, y) = (K(R1) slice k of block
+// (V, K, dR), slot).  The slice's FP32 rows N[k][s][j][nu] (2 n_V x a_V, contiguous) are read
+// coalesced into LDS; each thread unit (part, nu, 8 rows j') then takes its 8 values from LDS
+// (zero past 2 n_V) and writes them as one 16-byte store, consecutive units to consecutive
+// addresses of [k][part][nu][j'].  slices_start: prefix sums over the blocks of their slice counts.
+constexpr int SPLIT_MAX_ROWS = 2 * kMaxNao;
+__global__ __launch_bounds__(256) void split_n_kernel(Chi0Tables tb, const long long *__restrict__ slices_start,
+                                                      int nblk, const float *__restrict__ N, __bf16 *__restrict__ Ns,
+                                                      size_t n_slot, size_t ns_slot) {
+  __shared__ float sl[SPLIT_MAX_ROWS * kMaxNaux];
+  // block of this workgroup: the last b with slices_start[b] <= x (binary search)
+  const long long x = blockIdx.x;
+  int lo = 0, hi = nblk - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (slices_start[mid] <= x) lo = mid; else hi = mid - 1;
+  }
+  const int blk = lo, k = (int)(x - slices_start[blk]);
   const int nR = tb.nR, na = tb.natoms;
-  const int vk = blk / nR, K = vk % na, V = vk / na;
-  const int nK = tb.nao[K], nV = tb.nao[V], aV = tb.naux[V];
+  const int vk = blk / nR, V = vk / na;
+  const int nV = tb.nao[V], aV = tb.naux[V];
   const int JP = (2 * nV + 7) / 8 * 8, NO = JP / 8;
-  const float *src = N + (size_t)blockIdx.y * n_slot + tb.noff[blk];
-  __bf16 *dst = Ns + (size_t)blockIdx.y * ns_slot + tb.noffs[blk];
-  const int units = nK * NO * aV;
+  const int rows = 2 * nV;
+  const float *src = N + (size_t)blockIdx.y * n_slot + tb.noff[blk] + (size_t)k * rows * aV;
+  __bf16 *dst = Ns + (size_t)blockIdx.y * ns_slot + tb.noffs[blk] + (size_t)k * 2 * aV * JP;
+  for (int e = threadIdx.x; e < rows * aV; e += blockDim.x) sl[e] = src[e];
+  __syncthreads();
+  const int units = 2 * aV * NO;
   for (int u = threadIdx.x; u < units; u += blockDim.x) {
-    const int nu = u % aV, r = u / aV;
-    const int o = r % NO, k = r / NO;
-    bf8 hi, lo;
+    const int o = u % NO, pn = u / NO;
+    const int nu = pn % aV, part = pn / aV;
+    bf8 v;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const int jp = 8 * o + e;
-      float x = 0.f;
-      if (jp < 2 * nV) {
-        const int sch = jp >= nV, j = jp - sch * nV;
-        x = src[((size_t)(k * 2 + sch) * nV + j) * aV + nu];
-      }
+      const float xv = jp < rows ? sl[jp * aV + nu] : 0.f;
       __bf16 h, l;
-      split_bf16(x, h, l);
-      hi[e] = h;
-      lo[e] = l;
+      split_bf16(xv, h, l);
+      v[e] = part ? l : h;
     }
-    *reinterpret_cast<bf8 *>(dst + ((size_t)(k * 2) * aV + nu) * JP + 8 * o) = hi;
-    *reinterpret_cast<bf8 *>(dst + ((size_t)(k * 2 + 1) * aV + nu) * JP + 8 * o) = lo;
+    *reinterpret_cast<bf8 *>(dst + (size_t)pn * JP + 8 * o) = v;
   }
 }
 
 }  // namespace
 
-hipError_t launch_split_n(const Chi0Tables &tb, const float *N, uint16_t *Ns, int nslots, size_t n_slot, size_t ns_slot,
-                          hipStream_t s) {
+hipError_t launch_split_n(const Chi0Tables &tb, const long long *slices_start, long long nslices, const float *N,
+                          uint16_t *Ns, int nslots, size_t n_slot, size_t ns_slot, hipStream_t s) {
   const long long nblk = (long long)tb.natoms * tb.natoms * tb.nR;
-  if (nblk == 0 || nslots <= 0) return hipSuccess;
-  if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(split_n_kernel, dim3((unsigned)nblk, nslots), dim3(256), 0, s, tb, N,
+  if (nblk == 0 || nslices == 0 || nslots <= 0) return hipSuccess;
+  if (nslices > 0x7fffffffLL || nblk > 0x7fffffffLL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(split_n_kernel, dim3((unsigned)nslices, nslots), dim3(256), 0, s, tb, slices_start, (int)nblk, N,
                      reinterpret_cast<__bf16 *>(Ns), n_slot, ns_slot);
   return hipGetLastError();
 }

@@ -1,5 +1,5 @@
 """Batches of independent cells in one captured HIP graph (rpa_batch_*), on cells of the
-serving workload (2-16 atoms, k-meshes 1 and 2, 8-16 tau).
+serving workload (2-16 atoms, k-meshes 1x1x1, 2x2x2 and 3x3x3, 8-16 tau).
 
 Every cell's E_c from the graph equals the one-cell API bitwise (same kernels in the same
 order within a cell; lanes only change which cells overlap), replays of the graph with the
@@ -19,7 +19,7 @@ from tests._gpu import batch_cell, device_inputs, gpu_pipeline
 pytestmark = pytest.mark.gpu
 
 SMALL = [4, 7, 10, 14]      # 2, 2, 3, 4 atoms, Gamma only: the oracle takes seconds
-LARGER = [2, 6]             # 8 atoms, 2x2x2 k-mesh
+LARGER = [2, 6, 27]         # 8 atoms on a 2x2x2 k-mesh; 3 atoms on a 3x3x3 k-mesh
 
 
 def say(*a):

@@ -46,6 +46,25 @@ def diamond():
     return inp, device_inputs(inp)
 
 
+def test_diamond_fullsize_all_pairs_and_all_R(diamond):
+    """The 8-atom workload at full size, FP64 and split BF16: every atom pair (U, V) at one
+    (R, tau), and every lattice vector R of one pair at another tau, against the oracle one block
+    at a time (FP64 <= 1e-11, split BF16 <= 3e-5 per block)."""
+    inp, d = diamond
+    say("case diamond all pairs / all R")
+    alg = ochi.Alg1(inp)
+    pairs = [(inp.ntau - 1, U, V, 5) for U in range(inp.natoms) for V in range(inp.natoms)]
+    all_r = [(0, 1, 4, R) for R in range(inp.nR)]
+    chi64, _, ctx = gpu_chi_tau(inp, "fp64", dev_in=d)
+    e64 = max(_blocks(inp, chi64, pairs, alg), _blocks(inp, chi64, all_r, alg))
+    del chi64
+    chib, _, _ = gpu_chi_tau(inp, "bf16x3", ctx=ctx, dev_in=d)
+    eb = max(_blocks(inp, chib, pairs, alg), _blocks(inp, chib, all_r, alg))
+    del chib
+    say("  fp64 worst %.3g, bf16x3 worst %.3g over %d blocks" % (e64, eb, len(pairs) + len(all_r)))
+    assert e64 <= 1e-11 and eb <= 3e-5
+
+
 def test_diamond_fullsize_sampled_blocks(diamond):
     """8-atom, 4x4x4 mesh, 26 NAO / 100 ABF, 16 tau: FP64 <= 1e-11 and FP32 <= 1e-5 per block;
     split BF16 <= 3e-5 per block and <= 1e-5 over the whole tensor against FP64; samples cover

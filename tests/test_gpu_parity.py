@@ -19,6 +19,9 @@ pytestmark = pytest.mark.gpu
 FP64_TOL = 1e-11
 FP32_TOL = 1e-5
 CHI_TOL = {"fp64": FP64_TOL, "fp32": FP32_TOL, "bf16x3": FP32_TOL}
+# per block (U, V) over all tau and R: an operand carried in 16 (split BF16) or 24 (FP32) bits
+# leaves single blocks scattered around the whole-tensor error
+BLOCK_TOL = {"fp64": FP64_TOL, "fp32": 3e-5, "bf16x3": 3e-5}
 EC_TOL = {"fp64": 1e-10, "fp32": 1e-6, "bf16x3": 1e-6}      # Ha/atom
 PRECISIONS = ["fp64", "fp32", "bf16x3"]
 
@@ -47,6 +50,30 @@ def _oracle_chi(inp, key, cache):
     return cache[key]
 
 
+def _check_blocks(inp, got, ref, precision):
+    """Every atom-pair block chi_UV (all tau and R) within the per-block bar, relative to the
+    block where it is not negligible (above 1e-3 of the largest block), else to the largest
+    entry; returns the worst relative block error."""
+    scale = np.abs(ref).max()
+    norms = {}
+    for U in range(inp.natoms):
+        for V in range(inp.natoms):
+            mu = slice(inp.aux_off[U], inp.aux_off[U] + inp.naux[U])
+            nu = slice(inp.aux_off[V], inp.aux_off[V] + inp.naux[V])
+            norms[U, V] = (np.linalg.norm(ref[:, :, mu, nu]), mu, nu)
+    big = max(n for n, _, _ in norms.values())
+    worst = 0.0
+    for (U, V), (n, mu, nu) in norms.items():
+        g, r = got[:, :, mu, nu], ref[:, :, mu, nu]
+        if n > 1e-3 * big:
+            e = rel(g, r)
+            worst = max(worst, e)
+            assert e <= BLOCK_TOL[precision], (U, V, e)
+        else:
+            assert np.abs(g - r).max() <= BLOCK_TOL[precision] * scale, (U, V)
+    return worst
+
+
 @pytest.mark.parametrize("idx", range(len(MICRO)))
 @pytest.mark.parametrize("precision", PRECISIONS)
 def test_chi_tau_micro(idx, precision, oracle_cache):
@@ -57,9 +84,10 @@ def test_chi_tau_micro(idx, precision, oracle_cache):
     chi, _, _ = gpu_chi_tau(inp, precision)
     got = chi.cpu().numpy()
     err = rel(got, ref)
-    say("  rel err", err)
     assert np.all(np.isfinite(got))
     assert err <= CHI_TOL[precision]
+    worst = _check_blocks(inp, got, ref, precision)
+    say("  rel err", err, "worst block", worst)
 
 
 @pytest.mark.parametrize("precision", PRECISIONS)
@@ -71,8 +99,11 @@ def test_chi_tau_tiny_workload(precision, oracle_cache):
     got = chi.cpu().numpy()
     err = rel(got, ref)
     per_tau = max(rel(got[t], ref[t]) for t in range(inp.ntau))
-    say("  rel err", err, "max per-tau", per_tau, "flops", plan.flops())
+    worst = _check_blocks(inp, got, ref, precision)
+    say("  rel err", err, "max per-tau", per_tau, "worst block", worst, "flops", plan.flops())
     assert err <= CHI_TOL[precision]
+    # the stricter per-tau maximum (survey reading of the chi error metric) within the same bar
+    assert per_tau <= CHI_TOL[precision]
 
 
 @pytest.mark.parametrize("case", ["cfg0", "micro1"])
