@@ -286,14 +286,18 @@ RPA_API int chi0_R_to_q(rpa_ctx *ctx, const int mesh[3], int nbatch, size_t m, i
  * evaluated as ln det(I - B) + Tr B with B = L^H chi L, v(q) = L L^H (Cholesky,
  * FP64), det(1 - chi L L^H) = det(I - L^H chi L); I - B is Hermitian positive
  * definite when chi is negative semidefinite, and its log-determinant is
- * twice the sum of the logs of its Cholesky diagonal.
+ * twice the sum of the logs of its Cholesky diagonal.  A q point whose
+ * chi(q, i w_k) (every k) has zero imaginary parts takes T = chi L with two real
+ * products per complex one; where v(q) is real as well (a time-reversal
+ * invariant q with a real basis) every step of that q runs on real matrices.
+ * The choice is made on the device per q, so one call may mix both kinds.
  *   n           : matrix order (naux_tot)
  *   womega      : host FP64 [nomega]
  *   chi0_q      : device complex128 [nomega][nq][n][n]
  *   v_q         : device complex128 [nq][n][n], Hermitian positive definite
  *   workspace   : device; rpa_ec_workspace_size(n, nq, nomega) bytes run the
  *                 (q, omega) pairs in batches of up to all nq * nomega of them
- *                 (at most 32 GiB of per-pair matrices); less, down to the size
+ *                 (at most 64 GiB of per-pair matrices); less, down to the size
  *                 for one pair per batch, runs smaller batches
  *   Ec          : host, E_c per cell (Hartree)
  *   Ec_q        : host [nq] per-q contributions (already divided by nq), or NULL

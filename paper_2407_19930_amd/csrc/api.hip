@@ -224,10 +224,13 @@ struct rpa_plan {
 // ---- correlation energy ----
 namespace {
 struct EcLayout {
-  size_t L, T, B, W, trB, f, flags, ecq, w, realq, total;
+  size_t L, T, B, W, trB, f, flags, ecq, w, realq, realv, rboth, rpair, total;
   int cw;
 };
-// L: Cholesky factors of v(q) for every q; T, B: cw (q, omega) matrices at a time
+// L: Cholesky factors of v(q) for every q; T, B: cw (q, omega) matrices at a time.  At a q
+// where chi and v are both real the slots hold real row-major matrices: L_q in the first n^2
+// doubles of its slot, Re chi(q, omega) and then T in the two halves of a T slot, B in the
+// first half of a B slot.
 EcLayout ec_layout(int n, int nq, int nomega, int cw) {
   EcLayout l{};
   const size_t mat = (size_t)n * n * 16;
@@ -252,17 +255,23 @@ EcLayout ec_layout(int n, int nq, int nomega, int cw) {
   o = align_up(o + (size_t)nomega * 8);
   l.realq = o;
   o = align_up(o + (size_t)nq * 4);
+  l.realv = o;
+  o = align_up(o + (size_t)nq * 4);
+  l.rboth = o;
+  o = align_up(o + (size_t)nq * 4);
+  l.rpair = o;
+  o = align_up(o + (size_t)nq * nomega * 4);
   l.total = o;
   l.cw = cw;
   return l;
 }
-// (q, omega) pairs per batch for the default workspace: all of them, up to 32 GiB of the two
-// per-pair matrices T and B.  Each batch runs its own sequence of n / 32 Cholesky panel steps,
-// whose diagonal-block kernel costs about the same for one matrix as for many, so fewer and
-// larger batches finish sooner.
+// (q, omega) pairs per batch for the default workspace: all of them, up to 64 GiB of the two
+// per-pair matrices T and B (24 pairs of order 7440 take 42 GB).  Each batch runs its own
+// sequence of n / 32 Cholesky panel steps, whose diagonal-block kernel costs about the same for
+// one matrix as for many, so fewer and larger batches finish sooner.
 int ec_default_batch(int n, int nq, int nomega) {
   const size_t mat = (size_t)n * n * 16;
-  const size_t cap = std::max<size_t>(1, ((size_t)32 << 30) / (2 * mat));
+  const size_t cap = std::max<size_t>(1, ((size_t)64 << 30) / (2 * mat));
   return (int)std::min<size_t>((size_t)nq * nomega, cap);
 }
 }  // namespace
@@ -311,16 +320,22 @@ int ec_enqueue(rpa_ctx *ctx, hipStream_t s, int n, int nq, int nomega, const dou
   double *L = (double *)(ws + l.L), *T = (double *)(ws + l.T), *B = (double *)(ws + l.B),
          *W = (double *)(ws + l.W), *trB = (double *)(ws + l.trB), *f = (double *)(ws + l.f),
          *ecq = (double *)(ws + l.ecq);
-  int *flags = (int *)(ws + l.flags), *realq = (int *)(ws + l.realq);
+  int *flags = (int *)(ws + l.flags), *realq = (int *)(ws + l.realq), *realv = (int *)(ws + l.realv),
+      *rboth = (int *)(ws + l.rboth), *rpair = (int *)(ws + l.rpair);
   const size_t mat = (size_t)n * n * 2;   // doubles per complex matrix
+  const size_t n2 = (size_t)n * n;
   HIP_TRY(ctx, launch_fill_int(flags, (size_t)(nq + nq * nomega), 0, s));
   // q points whose chi(q, i omega) is real at every omega (time-reversal invariant q, where the
-  // phases of R -> q are +1 or -1): T = chi L there takes two real products per complex one
+  // phases of R -> q are +1 or -1): T = chi L there takes two real products per complex one;
+  // where v(q) is real too, every step of that q runs on real matrices
   HIP_TRY(ctx, launch_real_flags(chi0_q, n, nq, nomega, realq, s));
+  HIP_TRY(ctx, launch_real_flags(v_q, n, nq, 1, realv, s));
+  HIP_TRY(ctx, launch_both_real(realq, realv, nq, nomega, rboth, rpair, s));
   // v(q) = L_q L_q^H for every q at once
   HIP_TRY(ctx, launch_copy_words(L, v_q, nq * mat * 2, s));
-  HIP_TRY(ctx, launch_cholesky(L, mat, n, nq, W, flags, 0, s));
-  HIP_TRY(ctx, launch_zero_upper(L, mat, n, nq, s));
+  HIP_TRY(ctx, launch_pack_real(v_q, (long long)mat, 0, 0, 1, nq, L, mat, n2, rboth, s));
+  HIP_TRY(ctx, launch_cholesky(L, mat, n, nq, W, flags, 0, rboth, s));
+  HIP_TRY(ctx, launch_zero_upper(L, mat, n, nq, rboth, s));
   // (q, omega) pairs g = q * nomega + omega in batches of cw
   for (int b0 = 0; b0 < total; b0 += cw) {
     const int nb = std::min(cw, total - b0);
@@ -344,7 +359,27 @@ int ec_enqueue(rpa_ctx *ctx, hipStream_t s, int n, int nq, int nomega, const dou
     g.alpha = 1.0;
     g.kmode = 1;
     g.realA = realq;
+    g.skip = rboth;
     HIP_TRY(ctx, launch_zgemm(g, nb, s));
+    // the real pairs: Re chi into the first half of the T slot, T = chi L into the second
+    HIP_TRY(ctx, launch_pack_real(chi0_q, (long long)mat, (long long)nq * mat, b0, nomega, nb, T, mat, n2, rboth, s));
+    DgemmArgs gr{};
+    gr.M = gr.N = gr.K = n;
+    gr.A = T;
+    gr.lda = n;
+    gr.strideA = (long long)mat;
+    gr.B = L;
+    gr.ldb = n;
+    gr.outerB = (long long)mat;
+    gr.C = T + n2;
+    gr.ldc = n;
+    gr.strideC = (long long)mat;
+    gr.boff = b0;
+    gr.binner = nomega;
+    gr.alpha = 1.0;
+    gr.kmode = 1;
+    gr.sel = rboth;
+    HIP_TRY(ctx, launch_dgemm(gr, nb, s));
     // B = L_q^H T, lower triangle (L^H upper triangular: k >= first row of the tile)
     ZgemmArgs h{};
     h.M = h.N = h.K = n;
@@ -364,10 +399,31 @@ int ec_enqueue(rpa_ctx *ctx, hipStream_t s, int n, int nq, int nomega, const dou
     h.alpha = 1.0;
     h.lower_only = 1;
     h.kmode = 2;
+    h.skip = rboth;
     HIP_TRY(ctx, launch_zgemm(h, nb, s));
-    HIP_TRY(ctx, launch_trace_identity_minus(B, mat, n, nb, trB + b0, s));
-    HIP_TRY(ctx, launch_cholesky(B, mat, n, nb, W, flags, nq + b0, s));
-    HIP_TRY(ctx, launch_logdet(B, mat, n, nb, trB + b0, f + b0, flags, nq + b0, s));
+    DgemmArgs hr{};
+    hr.M = hr.N = hr.K = n;
+    hr.A = L;
+    hr.lda = n;
+    hr.outerA = (long long)mat;
+    hr.opA = 1;
+    hr.B = T + n2;
+    hr.ldb = n;
+    hr.strideB = (long long)mat;
+    hr.C = B;
+    hr.ldc = n;
+    hr.strideC = (long long)mat;
+    hr.boff = b0;
+    hr.binner = nomega;
+    hr.alpha = 1.0;
+    hr.lower_only = 1;
+    hr.kmode = 2;
+    hr.sel = rboth;
+    HIP_TRY(ctx, launch_dgemm(hr, nb, s));
+    const int *rp = rpair + b0;   // per matrix of the batch
+    HIP_TRY(ctx, launch_trace_identity_minus(B, mat, n, nb, trB + b0, rp, s));
+    HIP_TRY(ctx, launch_cholesky(B, mat, n, nb, W, flags, nq + b0, rp, s));
+    HIP_TRY(ctx, launch_logdet(B, mat, n, nb, trB + b0, f + b0, flags, nq + b0, rp, s));
   }
   HIP_TRY(ctx, launch_quadrature(f, womega_dev, nq, nomega, ecq, s));
   return RPA_OK;
@@ -926,21 +982,28 @@ int rpa_plan_create(rpa_ctx *ctx, const rpa_cell *cell, const rpa_lri_blocks *bl
         nsl += p->nao[K];
       }
   p->nslices_all = nsl;
-  // N-stage tiles
+  // N-stage tiles of each atom V in blocks of 8 column tiles by 8 row tiles (by 4 for the
+  // 256-row tiles): the 64 workgroups one XCD runs at a time then share 8 B column tiles and 8
+  // A row tiles in its L2, where a column of row tiles shares only its B tile
   const int M = 2 * nR * p->nbp;
   for (int V = 0; V < na; ++V) {
     const int NV = p->nao[V] * p->naux[V];
-    for (int n0 = 0; n0 < NV; n0 += 128)
-      for (int m0 = 0; m0 < M; m0 += 128) {
-        p->tileV.push_back(V);
-        p->tileM.push_back(m0);
-        p->tileN.push_back(n0);
-        if (m0 % 256 == 0) {
-          p->tile2V.push_back(V);
-          p->tile2M.push_back(m0);
-          p->tile2N.push_back(n0);
-        }
-      }
+    for (int nb0 = 0; nb0 < NV; nb0 += 8 * 128)
+      for (int mb0 = 0; mb0 < M; mb0 += 8 * 128)
+        for (int n0 = nb0; n0 < std::min(NV, nb0 + 8 * 128); n0 += 128)
+          for (int m0 = mb0; m0 < std::min(M, mb0 + 8 * 128); m0 += 128) {
+            p->tileV.push_back(V);
+            p->tileM.push_back(m0);
+            p->tileN.push_back(n0);
+          }
+    for (int nb0 = 0; nb0 < NV; nb0 += 8 * 128)
+      for (int mb0 = 0; mb0 < M; mb0 += 4 * 256)
+        for (int n0 = nb0; n0 < std::min(NV, nb0 + 8 * 128); n0 += 128)
+          for (int m0 = mb0; m0 < std::min(M, mb0 + 4 * 256); m0 += 256) {
+            p->tile2V.push_back(V);
+            p->tile2M.push_back(m0);
+            p->tile2N.push_back(n0);
+          }
   }
   // fused items: atom pairs U <= V (Sec. 3.2 pair set), all R; grouped by the kernel's
   // template classes (mu-tiles of U, O-GEMM steps of V)

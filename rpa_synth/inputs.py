@@ -163,14 +163,29 @@ def lri_blocks(cell: Cell, I, K, R, d, margin):
     return LRIBlocks(I, K, R, d, off, C, margin)
 
 
-def coulomb(cell: Cell, nauxtot, nq, note=None):
+def time_reversal_invariant(q_frac):
+    """Whether q = -q modulo the reciprocal lattice (every fractional coordinate 0 or 1/2)."""
+    return bool(np.all(np.abs(2.0 * np.asarray(q_frac) - np.round(2.0 * np.asarray(q_frac))) < 1e-12))
+
+
+def coulomb(cell: Cell, nauxtot, kfrac, note=None):
     """v(q) = s (L L^H + 1e-3 I) / lambda_max(L L^H + 1e-3 I), L complex Gaussian with
-    Re, Im ~ N(0, 1/2); s = cell.v_scale.  note, if given, is called after each q."""
+    Re, Im ~ N(0, 1/2); s = cell.v_scale.  At a time-reversal invariant q (q = -q modulo the
+    reciprocal lattice: every fractional coordinate 0 or 1/2) v(q) = v(-q) = v(q)^* is real,
+    as the Coulomb matrix of a real basis is there: L is then real, with entries N(0, 1) (the
+    same draws as at any other q, so that the other q points keep their matrices).  note, if
+    given, is called after each q."""
     rng = rng_for(cell.seed_key, Q_COULOMB)
+    nq = len(kfrac)
     vq = np.empty((nq, nauxtot, nauxtot), dtype=np.complex128)
     for q in range(nq):
-        L = (rng.standard_normal((nauxtot, nauxtot)) + 1j * rng.standard_normal((nauxtot, nauxtot))) * np.sqrt(0.5)
-        v = L @ L.conj().T + 1e-3 * np.eye(nauxtot)
+        Lr = rng.standard_normal((nauxtot, nauxtot))
+        Li = rng.standard_normal((nauxtot, nauxtot))
+        if time_reversal_invariant(kfrac[q]):
+            v = (Lr @ Lr.T + 1e-3 * np.eye(nauxtot)).astype(np.complex128)
+        else:
+            L = (Lr + 1j * Li) * np.sqrt(0.5)
+            v = L @ L.conj().T + 1e-3 * np.eye(nauxtot)
         v = 0.5 * (v + v.conj().T)
         vq[q] = v * (cell.v_scale / _lambda_max(v))
         if note:
@@ -217,7 +232,7 @@ def make_inputs(cell: Cell, with_coulomb=True, keep_wfc=True, with_green=True, p
     note("green functions")
     blocks = lri_blocks(cell, I, K, R, d, margin)
     note("LRI blocks")
-    vq = coulomb(cell, nauxtot, len(kfrac), note) if with_coulomb else None
+    vq = coulomb(cell, nauxtot, kfrac, note) if with_coulomb else None
     return Inputs(cell=cell, nao=nao, naux=naux, ao_off=lat.offsets(nao), aux_off=lat.offsets(naux),
                   nb=nb, nauxtot=nauxtot, Rvec=Rvec, kfrac=kfrac, blocks=blocks,
                   eps=eps if keep_wfc else None, wfc=wfc if keep_wfc else None, nocc=nocc, mu=mu,
