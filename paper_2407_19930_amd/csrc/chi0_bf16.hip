@@ -171,8 +171,8 @@ __device__ __forceinline__ void fused_bf16_body(const Chi0Tables &tb, int U, int
   // ---- Z terms (FP32 MFMA on the FP32 N blocks), as in the FP32 kernel
   const int negR = tb.bvk.neg(R);
   {
-    const float *NA = Nbuf + tb.noff[((size_t)U * natoms + V) * nR + R];
-    const float *NB = Nbuf + tb.noff[((size_t)V * natoms + U) * nR + negR];
+    const float *NA = Nbuf + uniform(tb.noff[((size_t)U * natoms + V) * nR + R]);
+    const float *NB = Nbuf + uniform(tb.noff[((size_t)V * natoms + U) * nR + negR]);
     if (wave_active && kept.z) {
       const int F = 2 * nU * nV;
       // views of the two N blocks (elements outside them read zero): the loads of ZB iterations
@@ -256,7 +256,10 @@ __device__ __forceinline__ void fused_bf16_body(const Chi0Tables &tb, int U, int
   // same time and share them in L2.  FP32 partial sums are folded into FP64 at the end of a pass
   // over the images once kFoldSlices slices have been added since the last fold, and at the end
   // of each run.  The cursor (e, k) runs two slices ahead of the slice being computed.
-  int e = 0, k = 0, g0 = 0, g1 = 0, run = 0;
+  // The run's NAO count and the table entry of the cursor stay in scalar registers: the LDS
+  // table is read when a run starts and when the cursor moves to another entry, so a run of one
+  // image (every run at the Gamma point) reads it once for all its slices.
+  int e = 0, k = 0, g0 = 0, g1 = 0, run = 0, nk_run = 0;
   auto advance = [&]() -> bool {   // next slice; true if the slice left is followed by a fold
     int e2 = e + 1, k2 = k;
     bool fold = false;
@@ -265,11 +268,12 @@ __device__ __forceinline__ void fused_bf16_body(const Chi0Tables &tb, int U, int
       e2 = g0;
       k2 = k + 1;
       bool run_end = false;
-      if (k2 == uniform(nbr_k[g0])) {
+      if (k2 == nk_run) {
         k2 = 0;
         e2 = g1;
         g0 = g1;
         g1 = e2 < ne ? uniform(nbr_g[e2]) : g1;
+        nk_run = e2 < ne ? uniform(nbr_k[e2]) : 0;
         run_end = true;
       }
       fold = run_end || run >= kFoldSlices;
@@ -282,11 +286,18 @@ __device__ __forceinline__ void fused_bf16_body(const Chi0Tables &tb, int U, int
   // N rows at the cursor into nb, and the cursor's C slice address into cnext (slice 0 again
   // once the cursor is past the end: in bounds, never used).
   const __bf16 *cnext = Cb;
+  int e_at = -1;
+  long long c_at = 0, n_at = 0;
   auto load_at = [&](NRows &nb) {
     const bool more = e < ne;
     const int ea = more ? e : 0, ka = more ? k : 0;
-    cnext = Cb + uniform(nbr_c[ea]) + (size_t)ka * sliceElems;
-    load_n(Ns + uniform(nbr_n[ea]) + (size_t)ka * nslice, nb);
+    if (ea != e_at) {
+      c_at = uniform(nbr_c[ea]);
+      n_at = uniform(nbr_n[ea]);
+      e_at = ea;
+    }
+    cnext = Cb + c_at + (size_t)ka * sliceElems;
+    load_n(Ns + n_at + (size_t)ka * nslice, nb);
   };
   bool fcur = false;   // fold after the slice being computed
   u4 rc[NLD];
@@ -370,6 +381,7 @@ __device__ __forceinline__ void fused_bf16_body(const Chi0Tables &tb, int U, int
   const int nsl = kept.y;
   if (ne > 0) {
     g1 = uniform(nbr_g[0]);
+    nk_run = uniform(nbr_k[0]);
     load_at(nb0);
     load_slice(cnext, rc);
     store_slice(0, rc);

@@ -446,8 +446,8 @@ __global__ __launch_bounds__(FU_THREADS) void fused_kernel(Chi0Tables tb, PairIt
   // ---- Z terms: contraction over (s, i, j) of N(U,V,R)[j][s][i][mu] and N(V,U,-R)[i][1-s][j][nu]
   const int negR = tb.bvk.neg(R);
   {
-    const T *NA = Nbuf + tb.noff[((size_t)U * natoms + V) * nR + R];
-    const T *NB = Nbuf + tb.noff[((size_t)V * natoms + U) * nR + negR];
+    const T *NA = Nbuf + uniform(tb.noff[((size_t)U * natoms + V) * nR + R]);
+    const T *NB = Nbuf + uniform(tb.noff[((size_t)V * natoms + U) * nR + negR]);
     if (wave_active && kept.z) {
       const int F = 2 * nU * nV;
       // views of the two N blocks (elements outside them read zero): the loads of ZB iterations

@@ -149,21 +149,25 @@ __global__ __launch_bounds__(ZT) void zgemm_kernel(ZgemmArgs g, unsigned bytesA,
       }
 }
 
-// Real batched GEMM, C = alpha op(A) op(B) + beta C, 128 x 128 output tile per workgroup of 4
-// waves (each 64 x 64: 4 x 4 MFMA tiles of 16 x 16), K step 16 through double-buffered LDS tiles
-// [k][row] with row r of k-row kk at r ^ dswz(kk): the MFMA operand reads (16 rows of four k)
-// then take the two LDS cycles a 64-lane 8-byte read needs.  Every K-loop load is a raw buffer
+// Real batched GEMM, C = alpha op(A) op(B) + beta C, a 128 x BN output tile per workgroup of 4
+// waves: BN = 128 as 2 x 2 waves of 64 x 64 (4 x 4 MFMA tiles of 16 x 16), BN = 32 (products with
+// at most 32 columns, such as the Cholesky panel updates) as 4 x 1 waves of 32 x 32.  K step 16
+// through double-buffered LDS tiles [k][row] with row r of k-row kk at r ^ dswz(kk): the MFMA
+// operand reads (16 rows of four k) then take the two LDS cycles a 64-lane 8-byte read needs.  Every K-loop load is a raw buffer
 // load of one element, unconditional (elements outside M, N or K read zero).  A thread's eight
 // elements of a tile are 16 consecutive k of a row per 16 lanes when the operand is stored
 // row by row along k, else 128 consecutive rows of one k per 128 threads, so each load
 // instruction reads whole cache lines.
 constexpr int DB = 128, DK = 16, DT = 256;
-static __device__ __forceinline__ int dswz(int kk) { return (kk & 15) << 3; }
+template <int W> static __device__ __forceinline__ int dswz(int kk) { return ((kk & 15) << 3) & (W - 1); }
 
-template <int OPA, int OPB>
+template <int OPA, int OPB, int BN>
 __global__ __launch_bounds__(DT, 2) void dgemm_kernel(DgemmArgs g, unsigned bytesA, unsigned bytesB) {
-  __shared__ double As[2][DK][DB], Bs[2][DK][DB];
-  const int n0 = blockIdx.x * DB, m0 = blockIdx.y * DB, bz = blockIdx.z;
+  constexpr int WN = BN == 128 ? 2 : 1, WM = 4 / WN;        // waves along n and m
+  constexpr int TM = DB / (16 * WM), TN = BN / (16 * WN);   // MFMA tiles per wave
+  constexpr int NB = BN / 16;                               // B elements per thread and K step
+  __shared__ double As[2][DK][DB], Bs[2][DK][BN];
+  const int n0 = blockIdx.x * BN, m0 = blockIdx.y * DB, bz = blockIdx.z;
   if (g.lower_only && n0 > m0 + DB - 1) return;
   const int gb = g.boff + bz, bi = g.binner > 0 ? g.binner : 1;
   const int go = gb / bi, gi = gb - go * bi;
@@ -172,7 +176,7 @@ __global__ __launch_bounds__(DT, 2) void dgemm_kernel(DgemmArgs g, unsigned byte
   const double *B = g.B + (size_t)bz * g.strideB + (size_t)go * g.outerB + (size_t)gi * g.innerB;
   double *C = g.C + (size_t)bz * g.strideC;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int wm = w >> 1, wn = w & 1, col = lane & 15, grp = lane >> 4;
+  const int wm = w / WN, wn = w % WN, col = lane & 15, grp = lane >> 4;
 
   int kbeg = 0;
   if (g.kmode == 1) kbeg = n0;
@@ -180,9 +184,10 @@ __global__ __launch_bounds__(DT, 2) void dgemm_kernel(DgemmArgs g, unsigned byte
   kbeg = (kbeg / DK) * DK;
 
   // this thread's elements: (row, k) = (rc + 16 e, kc) in the along-k form, (rt, kt + 2 e) in
-  // the other
+  // the other (for B with BN columns: (ct, ktb + (256 / BN) e))
   const int kc = tid & 15, rc = tid >> 4, rt = tid & 127, kt = tid >> 7;
-  double ra[8], rb[8];
+  const int ct = tid % BN, ktb = tid / BN;
+  double ra[8], rb[NB];
   const __amdgpu_buffer_rsrc_t rA = buffer_view(A, bytesA), rB = buffer_view(B, bytesB);
   auto load = [&](int k0) {
 #pragma unroll
@@ -191,7 +196,10 @@ __global__ __launch_bounds__(DT, 2) void dgemm_kernel(DgemmArgs g, unsigned byte
       const unsigned ia = (unsigned)((OPA == 0 ? (size_t)(m0 + arow) * g.lda + k0 + akk
                                                : (size_t)(k0 + akk) * g.lda + m0 + arow) * 8);
       ra[e] = buffer_load<double>(rA, ((m0 + arow < g.M) & (k0 + akk < g.K)) ? ia : bytesA);
-      const int bkk = OPB == 0 ? kt + 2 * e : kc, bcol = OPB == 0 ? rt : rc + 16 * e;
+    }
+#pragma unroll
+    for (int e = 0; e < NB; ++e) {
+      const int bkk = OPB == 0 ? ktb + (DT / BN) * e : kc, bcol = OPB == 0 ? ct : rc + 16 * e;
       const unsigned ib = (unsigned)((OPB == 0 ? (size_t)(k0 + bkk) * g.ldb + n0 + bcol
                                                : (size_t)(n0 + bcol) * g.ldb + k0 + bkk) * 8);
       rb[e] = buffer_load<double>(rB, ((n0 + bcol < g.N) & (k0 + bkk < g.K)) ? ib : bytesB);
@@ -201,17 +209,20 @@ __global__ __launch_bounds__(DT, 2) void dgemm_kernel(DgemmArgs g, unsigned byte
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const int akk = OPA == 0 ? kc : kt + 2 * e, arow = OPA == 0 ? rc + 16 * e : rt;
-      As[buf][akk][arow ^ dswz(akk)] = ra[e];
-      const int bkk = OPB == 0 ? kt + 2 * e : kc, bcol = OPB == 0 ? rt : rc + 16 * e;
-      Bs[buf][bkk][bcol ^ dswz(bkk)] = rb[e];
+      As[buf][akk][arow ^ dswz<DB>(akk)] = ra[e];
+    }
+#pragma unroll
+    for (int e = 0; e < NB; ++e) {
+      const int bkk = OPB == 0 ? ktb + (DT / BN) * e : kc, bcol = OPB == 0 ? ct : rc + 16 * e;
+      Bs[buf][bkk][bcol ^ dswz<BN>(bkk)] = rb[e];
     }
   };
 
-  d4 acc[4][4];
+  d4 acc[TM][TN];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < TM; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = Mfma<double>::zero();
+    for (int b = 0; b < TN; ++b) acc[a][b] = Mfma<double>::zero();
 
   const int nk = g.K > kbeg ? (g.K - kbeg + DK - 1) / DK : 0;
   if (nk > 0) {                            // block-uniform
@@ -225,28 +236,27 @@ __global__ __launch_bounds__(DT, 2) void dgemm_kernel(DgemmArgs g, unsigned byte
 #pragma unroll
     for (int ks = 0; ks < DK / 4; ++ks) {
       const int kk = ks * 4 + grp;
-      double ar[4], br[4];
+      double ar[TM], br[TN];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        ar[q] = As[cur][kk][(wm * 64 + q * 16 + col) ^ dswz(kk)];
-        br[q] = Bs[cur][kk][(wn * 64 + q * 16 + col) ^ dswz(kk)];
-      }
+      for (int q = 0; q < TM; ++q) ar[q] = As[cur][kk][(wm * TM * 16 + q * 16 + col) ^ dswz<DB>(kk)];
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+      for (int q = 0; q < TN; ++q) br[q] = Bs[cur][kk][(wn * TN * 16 + q * 16 + col) ^ dswz<BN>(kk)];
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = Mfma<double>::fma(ar[a], br[b], acc[a][b]);
+      for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int b = 0; b < TN; ++b) acc[a][b] = Mfma<double>::fma(ar[a], br[b], acc[a][b]);
     }
     if (it + 1 < nk) store(cur ^ 1);
     __syncthreads();
   }
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < TM; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+    for (int b = 0; b < TN; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int i = m0 + wm * 64 + a * 16 + Mfma<double>::row(grp, r);
-        const int j = n0 + wn * 64 + b * 16 + col;
+        const int i = m0 + wm * TM * 16 + a * 16 + Mfma<double>::row(grp, r);
+        const int j = n0 + wn * TN * 16 + b * 16 + col;
         if (i < g.M && j < g.N) {
           double *p = C + (size_t)i * g.ldc + j;
           double o = g.alpha * acc[a][b][r];
@@ -636,16 +646,29 @@ hipError_t launch_dgemm(const DgemmArgs &g, int batch, hipStream_t s) {
   const size_t ba = g.opA == 0 ? span(g.M, g.K, g.lda) : span(g.K, g.M, g.lda);
   const size_t bb = g.opB == 0 ? span(g.K, g.N, g.ldb) : span(g.N, g.K, g.ldb);
   if (ba > 0xffff0000u || bb > 0xffff0000u) return hipErrorInvalidValue;   // 32-bit buffer views
-  dim3 grid((g.N + DB - 1) / DB, (g.M + DB - 1) / DB, batch);
   const unsigned ua = (unsigned)ba, ub = (unsigned)bb;
+  if (g.N <= 32) {
+    // narrow products (panel updates): 128 x 32 tiles
+    dim3 grid(1, (g.M + DB - 1) / DB, batch);
+    if (g.opA == 0 && g.opB == 0)
+      hipLaunchKernelGGL((dgemm_kernel<0, 0, 32>), grid, dim3(DT), 0, s, g, ua, ub);
+    else if (g.opA == 0)
+      hipLaunchKernelGGL((dgemm_kernel<0, 1, 32>), grid, dim3(DT), 0, s, g, ua, ub);
+    else if (g.opB == 0)
+      hipLaunchKernelGGL((dgemm_kernel<1, 0, 32>), grid, dim3(DT), 0, s, g, ua, ub);
+    else
+      hipLaunchKernelGGL((dgemm_kernel<1, 1, 32>), grid, dim3(DT), 0, s, g, ua, ub);
+    return hipGetLastError();
+  }
+  dim3 grid((g.N + DB - 1) / DB, (g.M + DB - 1) / DB, batch);
   if (g.opA == 0 && g.opB == 0)
-    hipLaunchKernelGGL((dgemm_kernel<0, 0>), grid, dim3(DT), 0, s, g, ua, ub);
+    hipLaunchKernelGGL((dgemm_kernel<0, 0, 128>), grid, dim3(DT), 0, s, g, ua, ub);
   else if (g.opA == 0)
-    hipLaunchKernelGGL((dgemm_kernel<0, 1>), grid, dim3(DT), 0, s, g, ua, ub);
+    hipLaunchKernelGGL((dgemm_kernel<0, 1, 128>), grid, dim3(DT), 0, s, g, ua, ub);
   else if (g.opB == 0)
-    hipLaunchKernelGGL((dgemm_kernel<1, 0>), grid, dim3(DT), 0, s, g, ua, ub);
+    hipLaunchKernelGGL((dgemm_kernel<1, 0, 128>), grid, dim3(DT), 0, s, g, ua, ub);
   else
-    hipLaunchKernelGGL((dgemm_kernel<1, 1>), grid, dim3(DT), 0, s, g, ua, ub);
+    hipLaunchKernelGGL((dgemm_kernel<1, 1, 128>), grid, dim3(DT), 0, s, g, ua, ub);
   return hipGetLastError();
 }
 
@@ -673,8 +696,9 @@ hipError_t launch_both_real(const int *realchi, const int *realv, int nq, int no
 // columns, then the trailing matrix takes one rank-(np CB) update.  The trailing update reads
 // and writes the whole remaining matrix, so wider blocks cut that traffic (the diagonal-block
 // kernel stays CB wide: its cost grows with the cube of the width).  Measured: 4 panels for
-// n = 800 and 8 for n = 2400 (energy stage 124 -> 108 ms and 369 -> 304 ms against 1 panel).
-static int chol_panels(int n) { return n >= 1536 ? 8 : 4; }
+// n = 800 and 8 for n = 2400 (energy stage 124 -> 108 ms and 369 -> 304 ms against 1 panel),
+// 16 for n = 7440 (404 -> 399 ms against 8).
+static int chol_panels(int n) { return n >= 4096 ? 16 : (n >= 1536 ? 8 : 4); }
 hipError_t launch_cholesky(double *A, size_t stride, int n, int batch, double *Wscratch, int *flags, int flag_base,
                            const int *real, hipStream_t s) {
   hipError_t err = hipSuccess;
