@@ -3,7 +3,7 @@ kernels: real GEMM with 128 x 128 tiles, Cholesky pieces on real row-major matri
 points that stay complex (chi real with v complex, and both complex), in one call and in batches
 that mix them: per-q terms against the oracle's LU log-determinant (Sec. 2, E_c with
 Tr ln = ln det) on the same matrices.  n = 1600 spans several GEMM tiles with a ragged last
-one, and takes the Cholesky's wide-block form."""
+one, and takes the Cholesky's 8-panel blocks; n = 4160 its 16-panel blocks."""
 import numpy as np
 import pytest
 
@@ -90,3 +90,29 @@ def test_real_q_point_not_positive_definite_is_flagged():
     with pytest.raises(RpaError) as e:
         rpa_correlation_energy(ctx, w, torch.from_numpy(chi).cuda(), torch.from_numpy(vq).cuda(), ws)
     assert e.value.code == RPA_ERR_NOT_HPD
+
+
+def test_real_q_point_sixteen_panel_blocks():
+    """One real q point of order 4160 (the Cholesky's 16-panel blocks, a ragged last GEMM tile)
+    against the oracle's LU."""
+    import torch
+    from paper_2407_19930_amd import Context, rpa_correlation_energy, rpa_ec_workspace_size
+    n = 4160
+    rng = np.random.default_rng(11)
+    X = rng.standard_normal((n, n // 2))
+    c = -(X @ X.T)
+    c /= _norm2(c)
+    Y = rng.standard_normal((n, n))
+    v = Y @ Y.T + 0.1 * np.eye(n)
+    v /= _norm2(v)
+    chi = (0.5 * c).astype(np.complex128).reshape(1, 1, n, n)
+    vq = v.astype(np.complex128).reshape(1, n, n)
+    w = np.array([1.0])
+    f = ec_terms_lu(chi, vq)
+    ec_ref, _ = correlation_energy(f, w)
+    ctx = Context(0)
+    ws = torch.empty(rpa_ec_workspace_size(n, 1, 1), dtype=torch.uint8, device="cuda")
+    say("case energy real q, n %d" % n)
+    ec, _ = rpa_correlation_energy(ctx, w, torch.from_numpy(chi).cuda(), torch.from_numpy(vq).cuda(), ws)
+    say("  E_c gpu %.15g oracle LU %.15g" % (ec, ec_ref))
+    assert abs(ec - ec_ref) <= 1e-10 * abs(ec_ref)
