@@ -43,6 +43,16 @@ static __device__ __forceinline__ void split_bf16(float x, __bf16 &hi, __bf16 &l
   lo = (__bf16)(x - (float)hi);         // x - hi is exact in FP32
 }
 
+// The same split for two values at once, as packed pairs (element 0 in the low half): one
+// packed conversion per part, the hi values widened back by shift and mask.
+static __device__ __forceinline__ void split_bf16x2(float x0, float x1, unsigned &hi, unsigned &lo) {
+  typedef float f2 __attribute__((ext_vector_type(2)));
+  typedef __bf16 b2 __attribute__((ext_vector_type(2)));
+  hi = __builtin_bit_cast(unsigned, __builtin_convertvector((f2){x0, x1}, b2));
+  const float h0 = __builtin_bit_cast(float, hi << 16), h1 = __builtin_bit_cast(float, hi & 0xffff0000u);
+  lo = __builtin_bit_cast(unsigned, __builtin_convertvector((f2){x0 - h0, x1 - h1}, b2));
+}
+
 // Contraction slot of NAO index i of U in the chi GEMM.  With HC i-tiles of 16, lane group g
 // holds as its KW = 4 HC values the O accumulator registers r of tiles h, i = 16 h + 4 g + r,
 // in the order 4 h + r, so O feeds the next MFMA without moving between lanes.
@@ -343,16 +353,18 @@ __device__ __forceinline__ void fused_bf16_body(const Chi0Tables &tb, int U, int
 #pragma unroll
       for (int h = 0; h < HC; ++h) o[h] = onext[h];
       ogemm(nbnext, onext);
-      CVec bh, bl;
+      typedef unsigned UPairs __attribute__((ext_vector_type(KW / 2)));
+      UPairs ph, pl;
 #pragma unroll
       for (int h = 0; h < HC; ++h)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          __bf16 hi, lo;
-          split_bf16(o[h][r], hi, lo);
-          bh[4 * h + r] = hi;
-          bl[4 * h + r] = lo;
+        for (int r = 0; r < 4; r += 2) {
+          unsigned hi, lo;
+          split_bf16x2(o[h][r], o[h][r + 1], hi, lo);
+          ph[2 * h + r / 2] = hi;
+          pl[2 * h + r / 2] = lo;
         }
+      const CVec bh = __builtin_bit_cast(CVec, ph), bl = __builtin_bit_cast(CVec, pl);
       CVec ch1[M1], cl1[M1];
 #pragma unroll
       for (int m = M0; m < MT; ++m) {
