@@ -63,27 +63,36 @@ static __device__ __forceinline__ int nao_of_slot(int slot, int hc) {
 }
 
 // LRI blocks [mu][i][k] (FP64) -> per k, rows mu of 16 hc hi values then 16 hc lo values in
-// slot order (zero for slots past n_I), hc = 1 for n_I <= 16 else 2.
+// slot order (zero for slots past n_I), hc = 1 for n_I <= 16 else 2.  A workgroup takes
+// kPackMu rows mu of one block: each row C[mu][.][.] (n_I n_K <= 1024 values, contiguous) is
+// read once, coalesced, into LDS, and the k-major output rows are written from there.
+constexpr int kPackMu = 8;
 __global__ __launch_bounds__(256) void pack_cb_kernel(PackTables pt, const double *__restrict__ C,
                                                       __bf16 *__restrict__ Cb) {
+  __shared__ float row[kMaxNao * kMaxNao];
   const int b = blockIdx.x;
   const int a = pt.a[b], ni = pt.ni[b], nk = pt.nk[b];
+  const int mu0 = blockIdx.y * kPackMu;
+  if (mu0 >= a) return;                          // workgroup-uniform
   const int hc = ni > 16 ? 2 : 1, S = 16 * hc;
-  const long long total = (long long)nk * a * S;
   const double *src = C + pt.in_off[b];
   __bf16 *dst = Cb + pt.cb_off[b];
-  for (long long e = (long long)blockIdx.y * blockDim.x + threadIdx.x; e < total;
-       e += (long long)gridDim.y * blockDim.x) {
-    const int slot = (int)(e % S);
-    const long long t = e / S;
-    const int mu = (int)(t % a), k = (int)(t / a);
-    const int i = nao_of_slot(slot, hc);
-    const float x = i < ni ? (float)src[((long long)mu * ni + i) * nk + k] : 0.f;
-    __bf16 hi, lo;
-    split_bf16(x, hi, lo);
-    const long long row = ((long long)k * a + mu) * 2 * S;
-    dst[row + slot] = hi;
-    dst[row + S + slot] = lo;
+  const int mu1 = min(a, mu0 + kPackMu);
+  for (int mu = mu0; mu < mu1; ++mu) {
+    const double *r = src + (long long)mu * ni * nk;
+    for (int e = threadIdx.x; e < ni * nk; e += blockDim.x) row[e] = (float)r[e];
+    __syncthreads();
+    for (int e = threadIdx.x; e < nk * S; e += blockDim.x) {
+      const int k = e / S, slot = e - k * S;
+      const int i = nao_of_slot(slot, hc);
+      const float x = i < ni ? row[i * nk + k] : 0.f;
+      __bf16 hi, lo;
+      split_bf16(x, hi, lo);
+      const long long o = ((long long)k * a + mu) * 2 * S;
+      dst[o + slot] = hi;
+      dst[o + S + slot] = lo;
+    }
+    __syncthreads();
   }
 }
 
@@ -516,9 +525,9 @@ hipError_t launch_ks_hc(int ks, int hc, const Chi0Tables &tb, const PairItems &i
 int fused_bf16_ks_class(int js_class) { return 4 * js_class <= 32 ? 1 : 2; }
 
 hipError_t launch_pack_cb(const PackTables &pt, const double *C, uint16_t *Cb, long long maxblk, hipStream_t s) {
+  (void)maxblk;
   if (pt.nblk == 0) return hipSuccess;
-  const int ychunks = (int)((maxblk + 256 * 16 - 1) / (256 * 16));
-  dim3 grid(pt.nblk, ychunks > 0 ? ychunks : 1);
+  dim3 grid(pt.nblk, (kMaxNaux + kPackMu - 1) / kPackMu);
   hipLaunchKernelGGL(pack_cb_kernel, grid, dim3(256), 0, s, pt, C, reinterpret_cast<__bf16 *>(Cb));
   return hipGetLastError();
 }

@@ -11,7 +11,8 @@ runs Lanczos on the Hermitian L^H chi(q) L for every q of the mesh.  For the ser
 the one scale is set by the cell with the largest radius.
 
 Usage: python tests/golden/calibrate_vscale.py [config ...] [--workers N]
-(prints the V_SCALE entries; config 4 = the 64 serving cells)
+(prints the V_SCALE entries; config 33 = the 75-atom sheet on the 2x2x1 mesh, config 4 = the 64
+serving cells)
 """
 import concurrent.futures as cf
 import multiprocessing as mp
@@ -44,7 +45,7 @@ def main(argv):
         i = argv.index("--workers")
         workers = int(argv[i + 1])
         argv = argv[:i] + argv[i + 2:]
-    which = [int(a) for a in argv] or [0, 1, 2, 3, 4]
+    which = [int(a) for a in argv] or [0, 1, 2, 3, 33, 4]
     for i in which:
         if i == 4:
             cells = registry.serving_cells()
