@@ -224,7 +224,7 @@ struct rpa_plan {
 // ---- correlation energy ----
 namespace {
 struct EcLayout {
-  size_t L, T, B, W, trB, f, flags, ecq, w, realq, realv, rboth, rpair, total;
+  size_t L, T, B, W, trB, f, flags, ecq, w, realq, realv, rboth, rpair, counts, total;
   int cw;
 };
 // L: Cholesky factors of v(q) for every q; T, B: cw (q, omega) matrices at a time.  At a q
@@ -261,6 +261,8 @@ EcLayout ec_layout(int n, int nq, int nomega, int cw) {
   o = align_up(o + (size_t)nq * 4);
   l.rpair = o;
   o = align_up(o + (size_t)nq * nomega * 4);
+  l.counts = o;
+  o = align_up(o + 2 * 4);
   l.total = o;
   l.cw = cw;
   return l;
@@ -311,30 +313,41 @@ int ec_check_flags(rpa_ctx *ctx, const int *hflags, int nq, int nomega, const st
   return RPA_OK;
 }
 
-// The energy stage of one cell enqueued on stream s: kernels only (no host copy, no wait, no
-// memset), so it can be captured into a graph.  womega_dev: device [nomega].  Leaves the flags
-// and per-q terms (ecq[q], ecq[nq] = E_c) in the workspace at l.flags and l.ecq.
-int ec_enqueue(rpa_ctx *ctx, hipStream_t s, int n, int nq, int nomega, const double *womega_dev,
-               const double *chi0_q, const double *v_q, char *ws, const EcLayout &l) {
-  const int total = nq * nomega, cw = l.cw;
-  double *L = (double *)(ws + l.L), *T = (double *)(ws + l.T), *B = (double *)(ws + l.B),
-         *W = (double *)(ws + l.W), *trB = (double *)(ws + l.trB), *f = (double *)(ws + l.f),
-         *ecq = (double *)(ws + l.ecq);
+// First part of the energy stage: status flags cleared, and the kinds of the q points found on
+// the device (realq: chi real; realv: v real; rboth: both, the real layout; rpair: rboth per
+// (q, omega) pair; counts: {q points with the real layout, the others}).
+int ec_flags_enqueue(rpa_ctx *ctx, hipStream_t s, int n, int nq, int nomega, const double *chi0_q,
+                     const double *v_q, char *ws, const EcLayout &l) {
   int *flags = (int *)(ws + l.flags), *realq = (int *)(ws + l.realq), *realv = (int *)(ws + l.realv),
-      *rboth = (int *)(ws + l.rboth), *rpair = (int *)(ws + l.rpair);
-  const size_t mat = (size_t)n * n * 2;   // doubles per complex matrix
-  const size_t n2 = (size_t)n * n;
+      *rboth = (int *)(ws + l.rboth), *rpair = (int *)(ws + l.rpair), *counts = (int *)(ws + l.counts);
   HIP_TRY(ctx, launch_fill_int(flags, (size_t)(nq + nq * nomega), 0, s));
   // q points whose chi(q, i omega) is real at every omega (time-reversal invariant q, where the
   // phases of R -> q are +1 or -1): T = chi L there takes two real products per complex one;
   // where v(q) is real too, every step of that q runs on real matrices
   HIP_TRY(ctx, launch_real_flags(chi0_q, n, nq, nomega, realq, s));
   HIP_TRY(ctx, launch_real_flags(v_q, n, nq, 1, realv, s));
-  HIP_TRY(ctx, launch_both_real(realq, realv, nq, nomega, rboth, rpair, s));
+  HIP_TRY(ctx, launch_both_real(realq, realv, nq, nomega, rboth, rpair, counts, s));
+  return RPA_OK;
+}
+
+// The rest of the stage.  kinds: bit 0 if complex-layout q points may be present, bit 1 if
+// real-layout ones may; the kernels of an absent kind are not launched (the kernels of a present
+// kind skip the matrices of the other one).
+int ec_main_enqueue(rpa_ctx *ctx, hipStream_t s, int n, int nq, int nomega, const double *womega_dev,
+                    const double *chi0_q, const double *v_q, char *ws, const EcLayout &l, int kinds) {
+  const int total = nq * nomega, cw = l.cw;
+  double *L = (double *)(ws + l.L), *T = (double *)(ws + l.T), *B = (double *)(ws + l.B),
+         *W = (double *)(ws + l.W), *trB = (double *)(ws + l.trB), *f = (double *)(ws + l.f),
+         *ecq = (double *)(ws + l.ecq);
+  int *flags = (int *)(ws + l.flags), *realq = (int *)(ws + l.realq), *rboth = (int *)(ws + l.rboth),
+      *rpair = (int *)(ws + l.rpair);
+  const bool cplx = kinds & 1, rl = kinds & 2;
+  const size_t mat = (size_t)n * n * 2;   // doubles per complex matrix
+  const size_t n2 = (size_t)n * n;
   // v(q) = L_q L_q^H for every q at once
-  HIP_TRY(ctx, launch_copy_words(L, v_q, nq * mat * 2, s));
-  HIP_TRY(ctx, launch_pack_real(v_q, (long long)mat, 0, 0, 1, nq, L, mat, n2, rboth, s));
-  HIP_TRY(ctx, launch_cholesky(L, mat, n, nq, W, flags, 0, rboth, s));
+  if (cplx) HIP_TRY(ctx, launch_copy_words(L, v_q, nq * mat * 2, s));
+  if (rl) HIP_TRY(ctx, launch_pack_real(v_q, (long long)mat, 0, 0, 1, nq, L, mat, n2, rboth, s));
+  HIP_TRY(ctx, launch_cholesky(L, mat, n, nq, W, flags, 0, rboth, s, kinds));
   HIP_TRY(ctx, launch_zero_upper(L, mat, n, nq, rboth, s));
   // (q, omega) pairs g = q * nomega + omega in batches of cw
   for (int b0 = 0; b0 < total; b0 += cw) {
@@ -360,9 +373,10 @@ int ec_enqueue(rpa_ctx *ctx, hipStream_t s, int n, int nq, int nomega, const dou
     g.kmode = 1;
     g.realA = realq;
     g.skip = rboth;
-    HIP_TRY(ctx, launch_zgemm(g, nb, s));
+    if (cplx) HIP_TRY(ctx, launch_zgemm(g, nb, s));
     // the real pairs: Re chi into the first half of the T slot, T = chi L into the second
-    HIP_TRY(ctx, launch_pack_real(chi0_q, (long long)mat, (long long)nq * mat, b0, nomega, nb, T, mat, n2, rboth, s));
+    if (rl)
+      HIP_TRY(ctx, launch_pack_real(chi0_q, (long long)mat, (long long)nq * mat, b0, nomega, nb, T, mat, n2, rboth, s));
     DgemmArgs gr{};
     gr.M = gr.N = gr.K = n;
     gr.A = T;
@@ -379,7 +393,7 @@ int ec_enqueue(rpa_ctx *ctx, hipStream_t s, int n, int nq, int nomega, const dou
     gr.alpha = 1.0;
     gr.kmode = 1;
     gr.sel = rboth;
-    HIP_TRY(ctx, launch_dgemm(gr, nb, s));
+    if (rl) HIP_TRY(ctx, launch_dgemm(gr, nb, s));
     // B = L_q^H T, lower triangle (L^H upper triangular: k >= first row of the tile)
     ZgemmArgs h{};
     h.M = h.N = h.K = n;
@@ -400,7 +414,7 @@ int ec_enqueue(rpa_ctx *ctx, hipStream_t s, int n, int nq, int nomega, const dou
     h.lower_only = 1;
     h.kmode = 2;
     h.skip = rboth;
-    HIP_TRY(ctx, launch_zgemm(h, nb, s));
+    if (cplx) HIP_TRY(ctx, launch_zgemm(h, nb, s));
     DgemmArgs hr{};
     hr.M = hr.N = hr.K = n;
     hr.A = L;
@@ -419,14 +433,38 @@ int ec_enqueue(rpa_ctx *ctx, hipStream_t s, int n, int nq, int nomega, const dou
     hr.lower_only = 1;
     hr.kmode = 2;
     hr.sel = rboth;
-    HIP_TRY(ctx, launch_dgemm(hr, nb, s));
+    if (rl) HIP_TRY(ctx, launch_dgemm(hr, nb, s));
     const int *rp = rpair + b0;   // per matrix of the batch
     HIP_TRY(ctx, launch_trace_identity_minus(B, mat, n, nb, trB + b0, rp, s));
-    HIP_TRY(ctx, launch_cholesky(B, mat, n, nb, W, flags, nq + b0, rp, s));
+    HIP_TRY(ctx, launch_cholesky(B, mat, n, nb, W, flags, nq + b0, rp, s, kinds));
     HIP_TRY(ctx, launch_logdet(B, mat, n, nb, trB + b0, f + b0, flags, nq + b0, rp, s));
   }
   HIP_TRY(ctx, launch_quadrature(f, womega_dev, nq, nomega, ecq, s));
   return RPA_OK;
+}
+
+// The whole energy stage of one cell enqueued on stream s: kernels only (no host copy, no wait,
+// no memset), so it can be captured into a graph; both kinds of q point are provided for.
+// womega_dev: device [nomega].  Leaves the flags and per-q terms (ecq[q], ecq[nq] = E_c) in the
+// workspace at l.flags and l.ecq.
+int ec_enqueue(rpa_ctx *ctx, hipStream_t s, int n, int nq, int nomega, const double *womega_dev,
+               const double *chi0_q, const double *v_q, char *ws, const EcLayout &l) {
+  const int rc = ec_flags_enqueue(ctx, s, n, nq, nomega, chi0_q, v_q, ws, l);
+  if (rc != RPA_OK) return rc;
+  return ec_main_enqueue(ctx, s, n, nq, nomega, womega_dev, chi0_q, v_q, ws, l, 3);
+}
+
+// The energy stage for a caller that waits for it anyway: the kinds of q point present are read
+// back after the flags (8 bytes, one wait), so the launches of an absent kind are left out.
+int ec_enqueue_known(rpa_ctx *ctx, hipStream_t s, int n, int nq, int nomega, const double *womega_dev,
+                     const double *chi0_q, const double *v_q, char *ws, const EcLayout &l) {
+  int rc = ec_flags_enqueue(ctx, s, n, nq, nomega, chi0_q, v_q, ws, l);
+  if (rc != RPA_OK) return rc;
+  int counts[2] = {1, 1};
+  HIP_TRY(ctx, hipMemcpyAsync(counts, ws + l.counts, sizeof(counts), hipMemcpyDeviceToHost, s));
+  HIP_TRY(ctx, hipStreamSynchronize(s));
+  const int kinds = (counts[1] > 0 ? 1 : 0) | (counts[0] > 0 ? 2 : 0);
+  return ec_main_enqueue(ctx, s, n, nq, nomega, womega_dev, chi0_q, v_q, ws, l, kinds ? kinds : 3);
 }
 
 // phases exp(2 pi i q . n_R) for R -> q, the fractional part of q . n_R reduced before the 2 pi
@@ -1581,7 +1619,7 @@ int rpa_correlation_energy(rpa_ctx *ctx, int n, int nq, int nomega, const double
   HIP_TRY(ctx, hipMemcpyAsync(wdev, womega, nomega * 8, hipMemcpyHostToDevice, s));
   {
     Timed tm(ctx, "ec_stage");
-    const int rc = ec_enqueue(ctx, s, n, nq, nomega, wdev, chi0_q, v_q, ws, l);
+    const int rc = ec_enqueue_known(ctx, s, n, nq, nomega, wdev, chi0_q, v_q, ws, l);
     if (rc != RPA_OK) return rc;
   }
   std::vector<int> hflags(nq + nq * nomega);
@@ -1646,7 +1684,7 @@ int rpa_correlation_energy_noalloc(rpa_ctx *ctx, int n, int nq, int nomega, cons
   HIP_TRY(ctx, hipMemcpyAsync(wdev, womega, nomega * 8, hipMemcpyHostToDevice, s));
   {
     Timed tm(ctx, "ec_stage");
-    const int rc = ec_enqueue(ctx, s, n, nq, nomega, wdev, chi0_q, v_q, ws, l);
+    const int rc = ec_enqueue_known(ctx, s, n, nq, nomega, wdev, chi0_q, v_q, ws, l);
     if (rc != RPA_OK) return rc;
     HIP_TRY(ctx, launch_first_flag((const int *)(ws + l.flags), nq + nq * nomega, status, s));
   }

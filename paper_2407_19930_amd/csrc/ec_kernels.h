@@ -52,8 +52,10 @@ hipError_t launch_zgemm(const ZgemmArgs &g, int batch, hipStream_t s);
 hipError_t launch_dgemm(const DgemmArgs &g, int batch, hipStream_t s);
 // Matrix m of a batch (spaced `stride` doubles apart) is complex interleaved, or, where
 // real[m] != 0 (real may be null: none), real: its first n^2 doubles hold it row-major.
+// kinds: bit 0 set if the batch may hold complex matrices, bit 1 if it may hold real ones (the
+// launches of an absent kind are left out)
 hipError_t launch_cholesky(double *A, size_t stride, int n, int batch, double *Wscratch, int *flags, int flag_base,
-                           const int *real, hipStream_t s);
+                           const int *real, hipStream_t s, int kinds = 3);
 hipError_t launch_zero_upper(double *A, size_t stride, int n, int batch, const int *real, hipStream_t s);
 hipError_t launch_trace_identity_minus(double *B, size_t stride, int n, int batch, double *trB, const int *real,
                                        hipStream_t s);
@@ -64,9 +66,10 @@ hipError_t launch_logdet(const double *A, size_t stride, int n, int batch, const
 // g = boff + m), n2 elements each, only where sel[g / binner] != 0
 hipError_t launch_pack_real(const double *src, long long outer, long long inner, int boff, int binner, int nmat,
                             double *dst, size_t dstride, size_t n2, const int *sel, hipStream_t s);
-// both[q] = realchi[q] && realv[q]; pair[q nomega + k] = both[q]
+// both[q] = realchi[q] && realv[q]; pair[q nomega + k] = both[q]; counts[0] = number of q with
+// both real, counts[1] = the others
 hipError_t launch_both_real(const int *realchi, const int *realv, int nq, int nomega, int *both, int *pair,
-                            hipStream_t s);
+                            int *counts, hipStream_t s);
 hipError_t launch_fill_int(int *p, size_t n, int v, hipStream_t s);
 // real[q] = 1 if every imaginary part of the nomega matrices X[omega][q] (complex n x n) is zero,
 // else 0 (real must hold nq ints; it is cleared by the launcher's own kernel first)

@@ -290,6 +290,23 @@ __global__ void both_real_kernel(const int *realchi, const int *realv, int nq, i
   }
 }
 
+// counts[0] = number of q with chi and v real, counts[1] = nq - counts[0]; one workgroup.
+__global__ __launch_bounds__(256) void count_real_kernel(const int *realchi, const int *realv, int nq, int *counts) {
+  __shared__ int red[256];
+  int c = 0;
+  for (int q = threadIdx.x; q < nq; q += blockDim.x) c += (realchi[q] && realv[q]) ? 1 : 0;
+  red[threadIdx.x] = c;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    counts[0] = red[0];
+    counts[1] = nq - red[0];
+  }
+}
+
 // real[q] &= (imaginary part == 0) over the nomega matrices of q; the flags start at 1.
 __global__ __launch_bounds__(256) void real_flags_kernel(const double *__restrict__ X, size_t mat, int nq,
                                                          int nomega, int *__restrict__ real) {
@@ -438,17 +455,20 @@ __global__ __launch_bounds__(256) void chol_trsm_kernel(double *A, size_t stride
   for (int e = tid; e < 64 * CB; e += blockDim.x) {
     const int r = e / CB, c = e % CB;
     if (r0 + r >= n) continue;
+    const size_t o = (size_t)(r0 + r) * n + p + c;
+    if (rl) {   // real matrix: the real parts only
+      double s = 0.0;
+      for (int k = 0; k < CB; ++k) s += P[r][k].x * W[k][c].x;
+      Mr[o] = s;
+      continue;
+    }
     double2 s = make_double2(0.0, 0.0);
     for (int k = 0; k < CB; ++k) {
       const double2 a = P[r][k], w = W[k][c];
       s.x += a.x * w.x - a.y * w.y;
       s.y += a.x * w.y + a.y * w.x;
     }
-    const size_t o = (size_t)(r0 + r) * n + p + c;
-    if (rl)
-      Mr[o] = s.x;
-    else
-      M[o] = s;
+    M[o] = s;
   }
 }
 
@@ -682,10 +702,11 @@ hipError_t launch_pack_real(const double *src, long long outer, long long inner,
 }
 
 hipError_t launch_both_real(const int *realchi, const int *realv, int nq, int nomega, int *both, int *pair,
-                            hipStream_t s) {
+                            int *counts, hipStream_t s) {
   const int n = nq * std::max(nomega, 1);
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(both_real_kernel, dim3((n + 255) / 256), dim3(256), 0, s, realchi, realv, nq, nomega, both, pair);
+  hipLaunchKernelGGL(count_real_kernel, dim3(1), dim3(256), 0, s, realchi, realv, nq, counts);
   return hipGetLastError();
 }
 
@@ -700,12 +721,12 @@ hipError_t launch_both_real(const int *realchi, const int *realv, int nq, int no
 // 16 for n = 7440 (404 -> 399 ms against 8).
 static int chol_panels(int n) { return n >= 4096 ? 16 : (n >= 1536 ? 8 : 4); }
 hipError_t launch_cholesky(double *A, size_t stride, int n, int batch, double *Wscratch, int *flags, int flag_base,
-                           const int *real, hipStream_t s) {
+                           const int *real, hipStream_t s, int kinds) {
   hipError_t err = hipSuccess;
   // A[r0.., c0..c0+nc) -= A[r0.., k0..k0+K) A[c0..c0+nc, k0..k0+K)^H for rows r0 <= r < n: the
   // complex matrices by the complex GEMM, the real ones (if any) by the real GEMM
   auto update = [&](int r0, int c0, int nc, int k0, int K, int lower_only) -> hipError_t {
-    if (real) {
+    if (real && (kinds & 2)) {
       DgemmArgs d{};
       d.M = n - r0;
       d.N = nc;
@@ -728,6 +749,7 @@ hipError_t launch_cholesky(double *A, size_t stride, int n, int batch, double *W
       const hipError_t e = launch_dgemm(d, batch, s);
       if (e != hipSuccess) return e;
     }
+    if (!(kinds & 1)) return hipSuccess;
     ZgemmArgs g{};
     g.M = n - r0;
     g.N = nc;
