@@ -132,12 +132,14 @@ RPA_API int rpa_plan_stage_flops(const rpa_plan *plan, int stage, double *alg_fl
  *                  (0 when not measured)
  *   fused_single : 0 one fused launch per template class (the atom classes of the
  *                  uneven blocks: ABF tiles of U, NAO steps of V, NAO tiles of U) and tau;
- *                  1 or 2 (split-BF16 plans only) one launch for every class and every tau
+ *                  1, 2 or 3 (split-BF16 plans only) one launch for every class and every tau
  *                  of a chunk (rpa_plan_set_tau_batch), with the work of each tau in order of
  *                  decreasing size so that the compute units that finish early take the
  *                  small items; 1: workgroups of 8 waves, one per item (up to 128 ABF columns
  *                  of V); 2: workgroups of 4 waves, one per half of an item's columns (an
- *                  item with at most 64 columns takes one), two workgroups per compute unit
+ *                  item with at most 64 columns takes one), two workgroups per compute unit;
+ *                  3: workgroups of 4 waves, one per item, each wave two tiles of 16 columns
+ *                  (one wave per SIMD; each C fragment read feeds both tiles)
  *   nstage_bm    : rows of an N-stage output tile: 128 (4 waves), or 256 (8 waves, each
  *                  staged C tile used for twice the rows; split-BF16 N stage only)
  * Every variant computes the same chi; the item order leaves it bitwise unchanged,

@@ -640,7 +640,7 @@ struct BuildSteps {
           a.stats_stride = nitems * 3;
         }
       }
-      HIP_TRY(ctx, launch_fused_bf16_single(p->tb, a, halves ? 4 : 8, s));
+      HIP_TRY(ctx, launch_fused_bf16_single(p->tb, a, tu.fused_single, s));
       return RPA_OK;
     }
     for (int k = 0; k < ns; ++k)
@@ -741,7 +741,7 @@ static int autotune_impl(rpa_plan *p, const double *G_occ, const double *G_un, c
   if (rc == RPA_OK) rc = b.split();
   // fused kernel: item order of the per-class launches, then (split BF16) the single launch
   have = false;
-  for (int cand = 0; rc == RPA_OK && cand < (bf16 ? 4 : 2); ++cand) {
+  for (int cand = 0; rc == RPA_OK && cand < (bf16 ? 5 : 2); ++cand) {
     rpa_tuning c = best;
     c.fused_order = cand == 1 ? 1 : 0;
     c.fused_single = cand >= 2 ? cand - 1 : 0;
@@ -1380,7 +1380,7 @@ int rpa_plan_flops(const rpa_plan *p, double *alg, double *exec) {
 static bool tuning_valid(const rpa_plan *p, const rpa_tuning &t) {
   if (t.nstage_order != 0 && t.nstage_order != 1) return false;
   if (t.fused_order != 0 && t.fused_order != 1) return false;
-  if (t.fused_single != 0 && !((t.fused_single == 1 || t.fused_single == 2) && p->prec == RPA_BF16X3)) return false;
+  if (t.fused_single != 0 && !(t.fused_single >= 1 && t.fused_single <= 3 && p->prec == RPA_BF16X3)) return false;
   if (t.nstage_bm != 128 && !(t.nstage_bm == 256 && p->nbf16)) return false;
   return p->nbf16 ? t.nstage_kstep == 0 : (t.nstage_kstep == 16 || t.nstage_kstep == 32);
 }

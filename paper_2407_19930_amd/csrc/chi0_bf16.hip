@@ -110,12 +110,14 @@ struct FusedLds {
 };
 
 // One item (U <= V, R) of one tau: MT mu-tiles of U, KS O-GEMM steps of 32 over j' < 2 n_V, HC
-// i-tiles of U (n_U <= 16 HC), NW waves of 64 lanes.  Wave w owns the 16 ABF columns nu of V in
-// tile half NW + w, so a workgroup of 8 waves covers up to 128 columns and one of 4 waves the
-// half `half` of them (two workgroups per item when a_V > 64).  Every thread of the workgroup
+// i-tiles of U (n_U <= 16 HC), NW waves of 64 lanes, NU column tiles of 16 per wave.  Wave w owns
+// the ABF columns nu of V in the tiles NU (half NW + w) + t, t < NU: a workgroup of 8 waves with
+// one tile each, or of 4 waves with two, covers up to 128 columns; one of 4 waves with one tile
+// each covers the half `half` of them (two workgroups per item when a_V > 64).  With two tiles
+// per wave each C fragment read from LDS feeds both tiles' MFMAs.  Every thread of the workgroup
 // runs it; it leaves no barrier pending, and the caller must synchronise before the LDS is used
 // again.  stat: index of the item's statistics record (Screen::stats).
-template <int MT, int KS, int HC, int NW>
+template <int MT, int KS, int HC, int NW, int NU = 1>
 __device__ __forceinline__ void fused_bf16_body(const Chi0Tables &tb, int U, int V, int R, int half,
                                                 const float *__restrict__ Gp, const __bf16 *__restrict__ Cb,
                                                 const float *__restrict__ Nbuf, const __bf16 *__restrict__ Ns,
@@ -139,9 +141,15 @@ __device__ __forceinline__ void fused_bf16_body(const Chi0Tables &tb, int U, int
   const size_t plane = (size_t)nbp * nbp;
   const int tid = threadIdx.x, lane = tid & 63, w = uniform(half * NW + (tid >> 6));
   const int col = lane & 15, grp = lane >> 4;
-  const int nu = w * 16 + col;
-  const bool wave_active = w * 16 < aV;
-  const bool nu_ok = nu < aV;
+  int nu[NU];
+  bool nu_ok[NU], tile_on[NU];
+#pragma unroll
+  for (int t = 0; t < NU; ++t) {
+    nu[t] = (NU * w + t) * 16 + col;
+    tile_on[t] = (NU * w + t) * 16 < aV;
+    nu_ok[t] = nu[t] < aV;
+  }
+  const bool wave_active = tile_on[0];
   // neighbour table (the entries whose M terms the screening keeps; all without screening)
   const int3 kept =
       item_table<NT>(tb, sc, tb.nbr_cb, tb.noffs, U, V, R, nbr_c, nbr_n, nbr_k, nbr_g, lds.pos, lds.meta);
@@ -170,21 +178,25 @@ __device__ __forceinline__ void fused_bf16_body(const Chi0Tables &tb, int U, int
         al[h][ks][e] = lo;
       }
 
-  f4 acc[MT];
-  double acc64[MT][4];
+  f4 acc[NU][MT];
+  double acc64[NU][MT][4];
 #pragma unroll
-  for (int m = 0; m < MT; ++m) {
-    acc[m] = Mfma<float>::zero();
-#pragma unroll
-    for (int r = 0; r < 4; ++r) acc64[m][r] = 0.0;
-  }
-  auto flush = [&]() {
+  for (int t = 0; t < NU; ++t)
 #pragma unroll
     for (int m = 0; m < MT; ++m) {
+      acc[t][m] = Mfma<float>::zero();
 #pragma unroll
-      for (int r = 0; r < 4; ++r) acc64[m][r] += (double)acc[m][r];
-      acc[m] = Mfma<float>::zero();
+      for (int r = 0; r < 4; ++r) acc64[t][m][r] = 0.0;
     }
+  auto flush = [&]() {
+#pragma unroll
+    for (int t = 0; t < NU; ++t)
+#pragma unroll
+      for (int m = 0; m < MT; ++m) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc64[t][m][r] += (double)acc[t][m][r];
+        acc[t][m] = Mfma<float>::zero();
+      }
   };
 
   // ---- Z terms (FP32 MFMA on the FP32 N blocks), as in the FP32 kernel
@@ -201,7 +213,7 @@ __device__ __forceinline__ void fused_bf16_body(const Chi0Tables &tb, int U, int
       const __amdgpu_buffer_rsrc_t vA = buffer_view(NA, endA), vB = buffer_view(NB, endB);
       constexpr int ZB = 4;
       for (int f0 = 0; f0 < F; f0 += 4 * ZB) {
-        float bz[ZB], az[ZB][MT];
+        float bz[ZB][NU], az[ZB][MT];
 #pragma unroll
         for (int u = 0; u < ZB; ++u) {
           const int f = f0 + 4 * u + grp;
@@ -210,9 +222,13 @@ __device__ __forceinline__ void fused_bf16_body(const Chi0Tables &tb, int U, int
           const int s = fc / (nU * nV);
           const int rem = fc - s * nU * nV;
           const int i = rem / nV, j = rem - i * nV;
-          const unsigned ob =
-              (fv && nu_ok) ? (unsigned)((((i * 2 + 1 - s) * nV + j) * aV + nu) * sizeof(float)) : endB;
-          bz[u] = buffer_load<float>(vB, ob);
+#pragma unroll
+          for (int t = 0; t < NU; ++t) {
+            const unsigned ob = (fv && nu_ok[t])
+                                    ? (unsigned)((((i * 2 + 1 - s) * nV + j) * aV + nu[t]) * sizeof(float))
+                                    : endB;
+            bz[u][t] = buffer_load<float>(vB, ob);
+          }
 #pragma unroll
           for (int m = 0; m < MT; ++m) {
             const int mu = 16 * m + col;
@@ -224,7 +240,9 @@ __device__ __forceinline__ void fused_bf16_body(const Chi0Tables &tb, int U, int
 #pragma unroll
         for (int u = 0; u < ZB; ++u)
 #pragma unroll
-          for (int m = 0; m < MT; ++m) acc[m] = Mfma<float>::fma(az[u][m], bz[u], acc[m]);
+          for (int t = 0; t < NU; ++t)
+#pragma unroll
+            for (int m = 0; m < MT; ++m) acc[t][m] = Mfma<float>::fma(az[u][m], bz[u][t], acc[t][m]);
       }
     }
     flush();
@@ -257,17 +275,20 @@ __device__ __forceinline__ void fused_bf16_body(const Chi0Tables &tb, int U, int
   const size_t nslice = (size_t)2 * aV * JP;
   const unsigned nview = wave_active ? (unsigned)(nslice * sizeof(__bf16)) : 0u;
   struct NRows {
-    NVec h[KS], l[KS];
+    NVec h[NU][KS], l[NU][KS];
   };
   NRows nb0, nb1, nb2;
   auto load_n = [&](const __bf16 *nrow, NRows &dst) {
     const __amdgpu_buffer_rsrc_t r = buffer_view(nrow, nview);
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-      const unsigned o = (unsigned)(((size_t)nu * JP + 32 * ks + 8 * grp) * sizeof(__bf16));
-      dst.h[ks] = __builtin_bit_cast(NVec, __builtin_amdgcn_raw_buffer_load_b128(r, o, 0, 0));
-      dst.l[ks] = __builtin_bit_cast(NVec, __builtin_amdgcn_raw_buffer_load_b128(r, o + (unsigned)(aV * JP * 2), 0, 0));
-    }
+    for (int t = 0; t < NU; ++t)
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        const unsigned o = (unsigned)(((size_t)nu[t] * JP + 32 * ks + 8 * grp) * sizeof(__bf16));
+        dst.h[t][ks] = __builtin_bit_cast(NVec, __builtin_amdgcn_raw_buffer_load_b128(r, o, 0, 0));
+        dst.l[t][ks] =
+            __builtin_bit_cast(NVec, __builtin_amdgcn_raw_buffer_load_b128(r, o + (unsigned)(aV * JP * 2), 0, 0));
+      }
   };
   // Slice order: the entries e of U's neighbourhood come in runs [g0, g1) of one atom K (its
   // periodic images R1); a run is walked NAO k outer, image inner, so that the workgroups of
@@ -321,22 +342,26 @@ __device__ __forceinline__ void fused_bf16_body(const Chi0Tables &tb, int U, int
   bool fcur = false;   // fold after the slice being computed
   u4 rc[NLD];
   // O of a slice, A [G^un | G^occ](R) times the slice's split N rows (3 products)
-  auto ogemm = [&](const NRows &nb, f4 *o) __attribute__((always_inline)) {
+  auto ogemm = [&](const NRows &nb, f4 (*o)[HC]) __attribute__((always_inline)) {
 #pragma unroll
-    for (int h = 0; h < HC; ++h) o[h] = Mfma<float>::zero();
+    for (int t = 0; t < NU; ++t)
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks)
+      for (int h = 0; h < HC; ++h) o[t][h] = Mfma<float>::zero();
 #pragma unroll
-      for (int h = 0; h < HC; ++h) {
-        o[h] = BfMfma<8>::fma(ah[h][ks], nb.h[ks], o[h]);
-        o[h] = BfMfma<8>::fma(ah[h][ks], nb.l[ks], o[h]);
-        o[h] = BfMfma<8>::fma(al[h][ks], nb.h[ks], o[h]);
-      }
+    for (int t = 0; t < NU; ++t)
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+        for (int h = 0; h < HC; ++h) {
+          o[t][h] = BfMfma<8>::fma(ah[h][ks], nb.h[t][ks], o[t][h]);
+          o[t][h] = BfMfma<8>::fma(ah[h][ks], nb.l[t][ks], o[t][h]);
+          o[t][h] = BfMfma<8>::fma(al[h][ks], nb.h[t][ks], o[t][h]);
+        }
   };
   // The O GEMM runs one slice ahead of chi += C O: slice t takes O(t) from the slice before and
   // issues O(t + 1) on the MFMAs while O(t) is split into its bf16 parts, so the split does not
   // wait for its own GEMM.
-  f4 onext[HC];
+  f4 onext[NU][HC];
   // slice t: loads of slice t + 1's C (into rc) and of slice t + 2's N rows (into nbld), O GEMM of
   // t + 1 (N rows nbnext), chi += C O(t) with the C slice of t in LDS buffer cur, then rc to LDS.
   // live: t is a slice; live1: t + 1 is a slice.  Past the last slice the cursor reads slice 0
@@ -358,22 +383,29 @@ __device__ __forceinline__ void fused_bf16_body(const Chi0Tables &tb, int U, int
         cl0[m] = *reinterpret_cast<const CVec *>(cs + 16 * m * RS + 8 * HC);
       }
       __builtin_amdgcn_sched_barrier(0);
-      f4 o[HC];
+      f4 o[NU][HC];
 #pragma unroll
-      for (int h = 0; h < HC; ++h) o[h] = onext[h];
+      for (int t = 0; t < NU; ++t)
+#pragma unroll
+        for (int h = 0; h < HC; ++h) o[t][h] = onext[t][h];
       ogemm(nbnext, onext);
       typedef unsigned UPairs __attribute__((ext_vector_type(KW / 2)));
-      UPairs ph, pl;
+      CVec bh[NU], bl[NU];
 #pragma unroll
-      for (int h = 0; h < HC; ++h)
+      for (int t = 0; t < NU; ++t) {
+        UPairs ph, pl;
 #pragma unroll
-        for (int r = 0; r < 4; r += 2) {
-          unsigned hi, lo;
-          split_bf16x2(o[h][r], o[h][r + 1], hi, lo);
-          ph[2 * h + r / 2] = hi;
-          pl[2 * h + r / 2] = lo;
-        }
-      const CVec bh = __builtin_bit_cast(CVec, ph), bl = __builtin_bit_cast(CVec, pl);
+        for (int h = 0; h < HC; ++h)
+#pragma unroll
+          for (int r = 0; r < 4; r += 2) {
+            unsigned hi, lo;
+            split_bf16x2(o[t][h][r], o[t][h][r + 1], hi, lo);
+            ph[2 * h + r / 2] = hi;
+            pl[2 * h + r / 2] = lo;
+          }
+        bh[t] = __builtin_bit_cast(CVec, ph);
+        bl[t] = __builtin_bit_cast(CVec, pl);
+      }
       CVec ch1[M1], cl1[M1];
 #pragma unroll
       for (int m = M0; m < MT; ++m) {
@@ -381,17 +413,23 @@ __device__ __forceinline__ void fused_bf16_body(const Chi0Tables &tb, int U, int
         cl1[m - M0] = *reinterpret_cast<const CVec *>(cs + 16 * m * RS + 8 * HC);
       }
 #pragma unroll
-      for (int m = 0; m < M0; ++m) acc[m] = BfMfma<KW>::fma(ch0[m], bh, acc[m]);
+      for (int t = 0; t < NU; ++t) {
 #pragma unroll
-      for (int m = 0; m < M0; ++m) acc[m] = BfMfma<KW>::fma(ch0[m], bl, acc[m]);
+        for (int m = 0; m < M0; ++m) acc[t][m] = BfMfma<KW>::fma(ch0[m], bh[t], acc[t][m]);
 #pragma unroll
-      for (int m = 0; m < M0; ++m) acc[m] = BfMfma<KW>::fma(cl0[m], bh, acc[m]);
+        for (int m = 0; m < M0; ++m) acc[t][m] = BfMfma<KW>::fma(ch0[m], bl[t], acc[t][m]);
 #pragma unroll
-      for (int m = M0; m < MT; ++m) acc[m] = BfMfma<KW>::fma(ch1[m - M0], bh, acc[m]);
+        for (int m = 0; m < M0; ++m) acc[t][m] = BfMfma<KW>::fma(cl0[m], bh[t], acc[t][m]);
+      }
 #pragma unroll
-      for (int m = M0; m < MT; ++m) acc[m] = BfMfma<KW>::fma(ch1[m - M0], bl, acc[m]);
+      for (int t = 0; t < NU; ++t) {
 #pragma unroll
-      for (int m = M0; m < MT; ++m) acc[m] = BfMfma<KW>::fma(cl1[m - M0], bh, acc[m]);
+        for (int m = M0; m < MT; ++m) acc[t][m] = BfMfma<KW>::fma(ch1[m - M0], bh[t], acc[t][m]);
+#pragma unroll
+        for (int m = M0; m < MT; ++m) acc[t][m] = BfMfma<KW>::fma(ch1[m - M0], bl[t], acc[t][m]);
+#pragma unroll
+        for (int m = M0; m < MT; ++m) acc[t][m] = BfMfma<KW>::fma(cl1[m - M0], bh[t], acc[t][m]);
+      }
     }
     if (fcur) flush();
     fcur = f1;
@@ -421,19 +459,22 @@ __device__ __forceinline__ void fused_bf16_body(const Chi0Tables &tb, int U, int
   }
 
   // ---- epilogue: chi_UV(R) and chi_VU(-R) = chi_UV(R)^T, G scale removed
-  if (!wave_active || !nu_ok) return;
   const double scale = ldexp(negs, -(gexp[0] + gexp[1]));
   const size_t N = tb.nauxtot;
   const int au0 = tb.aux_off[U], av0 = tb.aux_off[V];
 #pragma unroll
-  for (int m = 0; m < MT; ++m) {
+  for (int t = 0; t < NU; ++t) {
+    if (!tile_on[t] || !nu_ok[t]) continue;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int mu = 16 * m + Mfma<float>::row(grp, r);
-      if (mu < aU) {
-        const double v = scale * acc64[m][r];
-        chi[((size_t)R * N + au0 + mu) * N + av0 + nu] = v;
-        if (U != V) chi[((size_t)negR * N + av0 + nu) * N + au0 + mu] = v;
+    for (int m = 0; m < MT; ++m) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int mu = 16 * m + Mfma<float>::row(grp, r);
+        if (mu < aU) {
+          const double v = scale * acc64[t][m][r];
+          chi[((size_t)R * N + au0 + mu) * N + av0 + nu[t]] = v;
+          if (U != V) chi[((size_t)negR * N + av0 + nu[t]) * N + au0 + mu] = v;
+        }
       }
     }
   }
@@ -463,7 +504,7 @@ __global__ __launch_bounds__(FB_THREADS) void fused_bf16_kernel(Chi0Tables tb, P
 // units of a slot come in order of decreasing work, and the hardware hands the workgroups to the
 // compute units in index order as they free up, so the launch ends on the smallest units.  The
 // item's class code (mt - 1) 4 + (ks - 1) 2 + (hc - 1) picks the instantiation of the body.
-template <int MT, int KS, int HC, int NW>
+template <int MT, int KS, int HC, int NW, int NU>
 __device__ __forceinline__ void single_item(const Chi0Tables &tb, const SingleLaunch &a, int item, int half, int slot,
                                             const FusedLds &lds) {
   Screen sc{nullptr, nullptr, nullptr, nullptr};
@@ -472,14 +513,17 @@ __device__ __forceinline__ void single_item(const Chi0Tables &tb, const SingleLa
     sc = Screen{a.gb + slot * nb3, a.gn + slot * nb3, a.gc + 2 * slot,
                 a.stats ? a.stats + (size_t)slot * a.stats_stride : nullptr};
   }
-  fused_bf16_body<MT, KS, HC, NW>(tb, a.U[item], a.V[item], a.R[item], half, a.Gp + slot * a.gp_stride,
+  fused_bf16_body<MT, KS, HC, NW, NU>(tb, a.U[item], a.V[item], a.R[item], half, a.Gp + slot * a.gp_stride,
                                   reinterpret_cast<const __bf16 *>(a.Cb), a.Nbuf + slot * a.n_stride,
                                   reinterpret_cast<const __bf16 *>(a.Ns) + slot * a.ns_stride, a.negs,
                                   a.gexp + 2 * slot, sc, item, a.chi + slot * a.chi_stride, lds);
 }
 
-template <int NW>
-__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2, 2))) void fused_bf16_single(
+// NW = 8, NU = 1: a workgroup per item, one column tile per wave; NW = 4, NU = 1: a workgroup per
+// half item; NW = 4, NU = 2: a workgroup per item, two column tiles per wave (one wave per SIMD,
+// with the register file of a whole SIMD).
+template <int NW, int NU>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3 - NU, 3 - NU))) void fused_bf16_single(
     Chi0Tables tb, SingleLaunch a) {
   __shared__ __align__(16) unsigned Cs[2 * kMaxNaux * fb_row_stride<2>()];
   __shared__ long long nbr_c[kMaxNbr], nbr_n[kMaxNbr];
@@ -488,10 +532,11 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2, 2)))
   const int w = blockIdx.x;
   const int slot = w / a.nitems;
   const int code = a.order[w - slot * a.nitems];
-  const int item = NW == 8 ? code : code >> 1, half = NW == 8 ? 0 : code & 1;
+  const bool halves = NW == 4 && NU == 1;
+  const int item = halves ? code >> 1 : code, half = halves ? code & 1 : 0;
   switch (a.cls[item]) {
 #define RPA_CLS(mt, ks, hc) \
-  case (mt - 1) * 4 + (ks - 1) * 2 + (hc - 1): single_item<mt, ks, hc, NW>(tb, a, item, half, slot, lds); break;
+  case (mt - 1) * 4 + (ks - 1) * 2 + (hc - 1): single_item<mt, ks, hc, NW, NU>(tb, a, item, half, slot, lds); break;
 #define RPA_CLS_MT(mt) RPA_CLS(mt, 1, 1) RPA_CLS(mt, 1, 2) RPA_CLS(mt, 2, 1) RPA_CLS(mt, 2, 2)
     RPA_CLS_MT(1) RPA_CLS_MT(2) RPA_CLS_MT(3) RPA_CLS_MT(4) RPA_CLS_MT(5) RPA_CLS_MT(6) RPA_CLS_MT(7) RPA_CLS_MT(8)
 #undef RPA_CLS_MT
@@ -887,13 +932,15 @@ hipError_t launch_nstage_bf16(const Chi0Tables &tb, const NTiles &tiles, int bm,
   return hipGetLastError();
 }
 
-hipError_t launch_fused_bf16_single(const Chi0Tables &tb, const SingleLaunch &a, int nw, hipStream_t s) {
+hipError_t launch_fused_bf16_single(const Chi0Tables &tb, const SingleLaunch &a, int mode, hipStream_t s) {
   const long long n = (long long)a.nslots * a.nitems;
   if (n == 0) return hipSuccess;
-  if (n > 0x7fffffffLL || (nw != 8 && nw != 4)) return hipErrorInvalidValue;
-  if (nw == 8)
-    hipLaunchKernelGGL(fused_bf16_single<8>, dim3((unsigned)n), dim3(512), 0, s, tb, a);
+  if (n > 0x7fffffffLL || mode < 1 || mode > 3) return hipErrorInvalidValue;
+  if (mode == 1)
+    hipLaunchKernelGGL((fused_bf16_single<8, 1>), dim3((unsigned)n), dim3(512), 0, s, tb, a);
+  else if (mode == 2)
+    hipLaunchKernelGGL((fused_bf16_single<4, 1>), dim3((unsigned)n), dim3(256), 0, s, tb, a);
   else
-    hipLaunchKernelGGL(fused_bf16_single<4>, dim3((unsigned)n), dim3(256), 0, s, tb, a);
+    hipLaunchKernelGGL((fused_bf16_single<4, 2>), dim3((unsigned)n), dim3(256), 0, s, tb, a);
   return hipGetLastError();
 }

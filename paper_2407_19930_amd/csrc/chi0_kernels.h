@@ -146,8 +146,10 @@ struct SingleLaunch {
 };
 // Class code of the single launch for (mt, ks, hc).
 inline int single_class(int mt, int ks, int hc) { return (mt - 1) * 4 + (ks - 1) * 2 + (hc - 1); }
-// nw: waves per workgroup, 8 (one workgroup per item) or 4 (one per half of an item's ABF columns)
-hipError_t launch_fused_bf16_single(const Chi0Tables &tb, const SingleLaunch &a, int nw, hipStream_t s);
+// mode 1: 8-wave workgroups, one per item; 2: 4-wave workgroups, one per half of an item's ABF
+// columns (a.order holds 2 item + half); 3: 4-wave workgroups, one per item, two column tiles per
+// wave
+hipError_t launch_fused_bf16_single(const Chi0Tables &tb, const SingleLaunch &a, int mode, hipStream_t s);
 
 // Screening bounds of one tau from FP64 G (see Screen): gb, then g and cut, then gn.
 hipError_t launch_screen_norms(const Chi0Tables &tb, const double *Gocc, const double *Gun, double theta, double *gb,

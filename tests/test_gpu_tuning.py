@@ -138,6 +138,10 @@ def test_set_tuning_rejects_out_of_range(cases):
         pb.set_tuning(0, 16, 0)             # the split-BF16 N stage has no K-step choice
     pb.set_tuning(1, 0, 1)
     pb.set_tuning(0, 0, 0, 1)
+    pb.set_tuning(0, 0, 0, 3)
+    with pytest.raises(RpaError) as e:
+        pb.set_tuning(0, 0, 0, 4)           # no such fused launch shape
+    assert e.value.code == RPA_ERR_ARG
     for bad in (0, inp.ntau + 1):
         with pytest.raises(RpaError) as e:
             pb.set_tau_batch(bad)
@@ -173,7 +177,7 @@ def test_tau_batch_and_single_launch(cases, case, precision):
         for slots in sorted({1, 2, inp.ntau}):
             grow = plan.set_tau_batch(slots)
             ws = torch.empty(max(grow, 1), dtype=torch.uint8, device="cuda")
-            for single in ((0, 1, 2) if precision == "bf16x3" else (0,)):
+            for single in ((0, 1, 2, 3) if precision == "bf16x3" else (0,)):
                 plan.set_tuning(0, k0, 0, single)
                 chi = _build(ctx, plan, inp, d, ws)
                 say("  theta %g slots %d single %d: equal %s" % (theta, slots, single, np.array_equal(chi, base)))
