@@ -116,3 +116,26 @@ def test_real_q_point_sixteen_panel_blocks():
     ec, _ = rpa_correlation_energy(ctx, w, torch.from_numpy(chi).cuda(), torch.from_numpy(vq).cuda(), ws)
     say("  E_c gpu %.15g oracle LU %.15g" % (ec, ec_ref))
     assert abs(ec - ec_ref) <= 1e-10 * abs(ec_ref)
+
+
+@pytest.mark.parametrize("keep", [(0,), (2,), (1, 2)])
+def test_calls_with_one_kind_of_q_point(keep):
+    """Calls whose q points are all real-layout (q 0), all complex (q 2), or complex with a real
+    chi (q 1) beside a complex one: the launches of the absent kind are left out, and the per-q
+    terms still match the oracle's LU."""
+    import torch
+    from paper_2407_19930_amd import Context, rpa_correlation_energy, rpa_ec_workspace_size
+    n = 300
+    chi, vq, w = _inputs(n, seed=13)
+    idx = list(keep)
+    chi = np.ascontiguousarray(chi[:, idx])
+    vq = np.ascontiguousarray(vq[idx])
+    f = ec_terms_lu(chi, vq)
+    ec_ref, perq_ref = correlation_energy(f, w)
+    ctx = Context(0)
+    nw, nq = chi.shape[:2]
+    ws = torch.empty(rpa_ec_workspace_size(n, nq, nw), dtype=torch.uint8, device="cuda")
+    say("case energy, q points", keep)
+    ec, perq = rpa_correlation_energy(ctx, w, torch.from_numpy(chi).cuda(), torch.from_numpy(vq).cuda(), ws)
+    np.testing.assert_allclose(perq, perq_ref, rtol=1e-10, atol=0)
+    assert abs(ec - ec_ref) <= 1e-10 * abs(ec_ref)
