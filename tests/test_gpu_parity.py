@@ -102,7 +102,7 @@ def test_chi_tau_tiny_workload(precision, oracle_cache):
     worst = _check_blocks(inp, got, ref, precision)
     say("  rel err", err, "max per-tau", per_tau, "worst block", worst, "flops", plan.flops())
     assert err <= CHI_TOL[precision]
-    # the stricter per-tau maximum (survey reading of the chi error metric) within the same bar
+    # the stricter per-tau maximum of the chi error (one reading of its metric) within the same bar
     assert per_tau <= CHI_TOL[precision]
 
 
