@@ -562,6 +562,9 @@ def main():
         log("screened build: %s" % rec_s)
     if chi64 is not None:
         del chi64
+    # the step's device buffers are not needed any more (the 2x2x1 sheet fills most of the HBM)
+    del ws, ws_ec, chi_w, chi_tau, big
+    torch.cuda.empty_cache()
 
     # the Green's functions of the step's input, built on the GPU from the eigenpairs (outside the
     # timed steps, which take G as given): one untimed and one timed call
