@@ -6,8 +6,9 @@ A step is one pass of the whole path on device-resident inputs:
 Default workload: the largest single-GPU cell, a 72-atom hexagonal sheet (a = 2.46 A, 26 NAO / 100 ABF
 per atom) with a bent triatomic 3 A above it (26/120 and 2 x 13/60), 15 A of vacuum, Gamma point,
 24 tau/omega points, 12 A cutoff, on the split-BF16 (3-term) path; seeded synthetic inputs.  The
-2x2x1 k-mesh of the same cell (`--workload sheet2x2x1`) quadruples every stage and does not fit
-the default 20 + 5 steps into a ten-minute run, so it is a separate command.
+2x2x1 k-mesh of the same cell (`--workload sheet2x2x1`) quadruples every stage (9.9 s per step),
+does not fit 20 + 5 steps into a ten-minute run, and leaves no room in the 288 GB for the FP64
+comparison, so it is a separate command (`--no-fp64-check`).
 
 Prints one JSON line.  `value` is the algorithmic flop count of the chi0 build (Algorithm 1
 with its N intermediate evaluated once per (V, K, R1-R)) divided by the wall time of the whole
