@@ -664,7 +664,7 @@ constexpr int NB_RS = 40;            // LDS row stride (bf16): 32 contraction va
 // the view's end, so offset plus load size never wraps).  BM: tile rows, 128 (4 waves) or 256
 // (8 waves, each B tile then serves twice the rows); 128 columns, waves of 64 x 64.
 template <int BM>
-__global__ __launch_bounds__(2 * BM) void nstage_bf16_kernel(Chi0Tables tb, NTiles tiles,
+__global__ __launch_bounds__(2 * BM) __attribute__((amdgpu_waves_per_eu(2))) void nstage_bf16_kernel(Chi0Tables tb, NTiles tiles,
                                                              const __bf16 *__restrict__ GTh,
                                                              const __bf16 *__restrict__ GTl, unsigned gt_bytes,
                                                              const __bf16 *__restrict__ Cth,
@@ -712,8 +712,10 @@ __global__ __launch_bounds__(2 * BM) void nstage_bf16_kernel(Chi0Tables tb, NTil
   const __amdgpu_buffer_rsrc_t cvh = buffer_view(Cth, ct_bytes), cvl = buffer_view(Ctl, ct_bytes);
   const int n0m = tb.bvk.n0, n1m = tb.bvk.n1, n2m = tb.bvk.n2;
 
-  u4 ra[2][2], rb[BG][2];                      // [group][part]
-  auto load = [&](int ks) {
+  // two register sets of the staged operands, [group][part]: the loads of K step ks + 2 are
+  // issued before the MFMAs of step ks and written to LDS after those of step ks + 1
+  u4 ra0[2][2], rb0[BG][2], ra1[2][2], rb1[BG][2];
+  auto load = [&](int ks, u4 (&ra)[2][2], u4 (&rb)[BG][2]) {
     // the 4 groups of the K step: wave-uniform table reads (scalar loads)
     int4 gq[4];
     long long oq[4];
@@ -759,7 +761,7 @@ __global__ __launch_bounds__(2 * BM) void nstage_bf16_kernel(Chi0Tables tb, NTil
       rb[q][1] = __builtin_bit_cast(u4, __builtin_amdgcn_raw_buffer_load_b128(cvl, ob, 0, 0));
     }
   };
-  auto store = [&](int buf) {
+  auto store = [&](int buf, const u4 (&ra)[2][2], const u4 (&rb)[BG][2]) {
 #pragma unroll
     for (int q = 0; q < 2; ++q)
 #pragma unroll
@@ -779,35 +781,46 @@ __global__ __launch_bounds__(2 * BM) void nstage_bf16_kernel(Chi0Tables tb, NTil
     for (int b = 0; b < 4; ++b) acc[a][b] = Mfma<float>::zero();
 
   const int nks = (ng + 3) / 4;
-  load(0);
-  store(0);
-  __syncthreads();
-  for (int ks = 0; ks < nks; ++ks) {
-    const int cur = ks & 1;
-    if (ks + 1 < nks) load(ks + 1);
-    bf8 ah[4], al[4], bh[4], bl[4];
+  // B fragments of the step first, then one row tile of A at a time (3 x 4 MFMAs per row tile,
+  // four independent accumulators between two products into the same one)
+  auto compute = [&](int cur) {
+    bf8 bh[4], bl[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int oa_ = (wm * 64 + q * 16 + col) * NB_RS + 8 * grp;
       const int ob_ = (wn * 64 + q * 16 + col) * NB_RS + 8 * grp;
-      ah[q] = *reinterpret_cast<const bf8 *>(&As[cur][0][oa_]);
-      al[q] = *reinterpret_cast<const bf8 *>(&As[cur][1][oa_]);
       bh[q] = *reinterpret_cast<const bf8 *>(&Bs[cur][0][ob_]);
       bl[q] = *reinterpret_cast<const bf8 *>(&Bs[cur][1][ob_]);
     }
 #pragma unroll
-    for (int tm = 0; tm < 4; ++tm)
+    for (int tm = 0; tm < 4; ++tm) {
+      const int oa_ = (wm * 64 + tm * 16 + col) * NB_RS + 8 * grp;
+      const bf8 ah = *reinterpret_cast<const bf8 *>(&As[cur][0][oa_]);
+      const bf8 al = *reinterpret_cast<const bf8 *>(&As[cur][1][oa_]);
 #pragma unroll
-      for (int tn = 0; tn < 4; ++tn) acc[tm][tn] = BfMfma<8>::fma(ah[tm], bh[tn], acc[tm][tn]);
+      for (int tn = 0; tn < 4; ++tn) acc[tm][tn] = BfMfma<8>::fma(ah, bh[tn], acc[tm][tn]);
 #pragma unroll
-    for (int tm = 0; tm < 4; ++tm)
+      for (int tn = 0; tn < 4; ++tn) acc[tm][tn] = BfMfma<8>::fma(ah, bl[tn], acc[tm][tn]);
 #pragma unroll
-      for (int tn = 0; tn < 4; ++tn) acc[tm][tn] = BfMfma<8>::fma(ah[tm], bl[tn], acc[tm][tn]);
-#pragma unroll
-    for (int tm = 0; tm < 4; ++tm)
-#pragma unroll
-      for (int tn = 0; tn < 4; ++tn) acc[tm][tn] = BfMfma<8>::fma(al[tm], bh[tn], acc[tm][tn]);
-    if (ks + 1 < nks) store(cur ^ 1);
+      for (int tn = 0; tn < 4; ++tn) acc[tm][tn] = BfMfma<8>::fma(al, bh[tn], acc[tm][tn]);
+    }
+  };
+  // Loads are unconditional: a K step past the last group reads zeros (its table entries are
+  // invalid, so every lane addresses the end of its view), which keeps the wait counts exact.
+  load(0, ra0, rb0);
+  load(1, ra1, rb1);
+  store(0, ra0, rb0);
+  __syncthreads();
+  for (int ks = 0; ks < nks; ks += 2) {
+    // step ks from LDS buffer 0; step ks + 1 is in ra1 / rb1
+    load(ks + 2, ra0, rb0);
+    compute(0);
+    if (ks + 1 >= nks) break;
+    store(1, ra1, rb1);
+    __syncthreads();
+    // step ks + 1 from LDS buffer 1; step ks + 2 is in ra0 / rb0
+    load(ks + 3, ra1, rb1);
+    compute(1);
+    if (ks + 2 < nks) store(0, ra0, rb0);
     __syncthreads();
   }
 
