@@ -160,9 +160,7 @@ struct rpa_plan {
   std::vector<int> nslices;                     // per atom U: sum of n_K over its neighbours
   std::vector<int> rows_start;
   std::vector<int4> row_info;
-  std::vector<long long> noff, noffs, slices_start;
-  long long nslices_all = 0;
-  const long long *d_slices_start = nullptr;
+  std::vector<long long> noff, noffs;
   long long n_elems = 0;                        // N buffer elements per tau
   long long ns_elems = 0;                       // split-BF16 N elements per tau (BF16X3 plans)
   std::vector<int> tileV, tileM, tileN;
@@ -589,8 +587,8 @@ struct BuildSteps {
   int split(int ns = 1) {
     if (!bf16) return RPA_OK;
     Timed tm(ctx, "split_n");
-    HIP_TRY(ctx, launch_split_n(p->tb, p->d_slices_start, p->nslices_all, (const float *)Nb, Nsp, ns,
-                                p->n_slot / sizeof(float), p->ns_slot / sizeof(uint16_t), s));
+    HIP_TRY(ctx, launch_split_n(p->tb, (const float *)Nb, Nsp, ns, p->n_slot / sizeof(float),
+                                p->ns_slot / sizeof(uint16_t), s));
     return RPA_OK;
   }
   // Screening bounds of tau t (when the plan screens).
@@ -1010,16 +1008,6 @@ int rpa_plan_create(rpa_ctx *ctx, const rpa_cell *cell, const rpa_lri_blocks *bl
         nso += (long long)p->nao[K] * 2 * p->naux[V] * ((2 * p->nao[V] + 7) / 8 * 8);
       }
   p->ns_elems = precision == RPA_BF16X3 ? nso : 0;
-  // K(R1) slices before each block (the split copy runs one workgroup per slice)
-  p->slices_start.resize(p->noff.size());
-  long long nsl = 0;
-  for (int V = 0; V < na; ++V)
-    for (int K = 0; K < na; ++K)
-      for (int r = 0; r < nR; ++r) {
-        p->slices_start[((size_t)V * na + K) * nR + r] = nsl;
-        nsl += p->nao[K];
-      }
-  p->nslices_all = nsl;
   // N-stage tiles of each atom V in blocks of 8 column tiles by 8 row tiles (by 4 for the
   // 256-row tiles): the 64 workgroups one XCD runs at a time then share 8 B column tiles and 8
   // A row tiles in its L2, where a column of row tiles shares only its B tile
@@ -1177,7 +1165,6 @@ int rpa_plan_create(rpa_ctx *ctx, const rpa_cell *cell, const rpa_lri_blocks *bl
                s_ncp = add(p->nbr_cp.data(), nblk * 8), s_rs = add(p->rows_start.data(), (na + 1) * 4),
                s_ri = add(p->row_info.data(), p->row_info.size() * 16), s_noff = add(p->noff.data(), p->noff.size() * 8),
                s_noffs = add(p->noffs.data(), p->noffs.size() * 8),
-               s_sls = add(p->slices_start.data(), p->slices_start.size() * 8),
                s_tV = add(p->tileV.data(), p->tileV.size() * 4), s_tM = add(p->tileM.data(), p->tileM.size() * 4),
                s_tN = add(p->tileN.data(), p->tileN.size() * 4), s_iU = add(p->itemU.data(), p->itemU.size() * 4),
                s_iV = add(p->itemV.data(), p->itemV.size() * 4), s_iR = add(p->itemR.data(), p->itemR.size() * 4),
@@ -1230,7 +1217,6 @@ int rpa_plan_create(rpa_ctx *ctx, const rpa_cell *cell, const rpa_lri_blocks *bl
   tb.row_info = (const int4 *)(d + secs[s_ri].off);
   tb.noff = I64(s_noff);
   tb.noffs = I64(s_noffs);
-  p->d_slices_start = I64(s_sls);
   tb.cp_stride = I32(s_cst);
   tb.nslices = I32(s_nsl);
   tb.nbr_cb = I64(s_ncb);

@@ -852,58 +852,53 @@ __global__ __launch_bounds__(2 * BM) __attribute__((amdgpu_waves_per_eu(2))) voi
 
 namespace {
 
-// Split-BF16 copy of N for the fused kernel's O GEMM: workgroup (x, y) = (K(R1) slice k of block
-// (V, K, dR), slot).  The slice's FP32 rows N[k][s][j][nu] (2 n_V x a_V, contiguous) are read
-// coalesced into LDS; each thread unit (part, nu, 8 rows j') then takes its 8 values from LDS
-// (zero past 2 n_V) and writes them as one 16-byte store, consecutive units to consecutive
-// addresses of [k][part][nu][j'].  slices_start: prefix sums over the blocks of their slice counts.
+// Split-BF16 copy of N for the fused kernel's O GEMM: workgroup (x, y) = (block (V, K, dR) of
+// index x, slot y), over the block's n_K slices in turn.  Each K(R1) slice's FP32 rows
+// N[k][s][j][nu] (2 n_V x a_V, contiguous) are read coalesced into LDS; each thread unit (part,
+// nu, 8 rows j') then takes its 8 values from LDS (zero past 2 n_V) and writes them as one 16-byte
+// store, consecutive units to consecutive addresses of [k][part][nu][j'].
 constexpr int SPLIT_MAX_ROWS = 2 * kMaxNao;
-__global__ __launch_bounds__(256) void split_n_kernel(Chi0Tables tb, const long long *__restrict__ slices_start,
-                                                      int nblk, const float *__restrict__ N, __bf16 *__restrict__ Ns,
-                                                      size_t n_slot, size_t ns_slot) {
+__global__ __launch_bounds__(256) void split_n_kernel(Chi0Tables tb, const float *__restrict__ N,
+                                                      __bf16 *__restrict__ Ns, size_t n_slot, size_t ns_slot) {
   __shared__ float sl[SPLIT_MAX_ROWS * kMaxNaux];
-  // block of this workgroup: the last b with slices_start[b] <= x (binary search)
-  const long long x = blockIdx.x;
-  int lo = 0, hi = nblk - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) / 2;
-    if (slices_start[mid] <= x) lo = mid; else hi = mid - 1;
-  }
-  const int blk = lo, k = (int)(x - slices_start[blk]);
+  const int blk = blockIdx.x;
   const int nR = tb.nR, na = tb.natoms;
-  const int vk = blk / nR, V = vk / na;
-  const int nV = tb.nao[V], aV = tb.naux[V];
+  const int vk = blk / nR, V = vk / na, K = vk - V * na;
+  const int nV = tb.nao[V], aV = tb.naux[V], nK = tb.nao[K];
   const int JP = (2 * nV + 7) / 8 * 8, NO = JP / 8;
   const int rows = 2 * nV;
-  const float *src = N + (size_t)blockIdx.y * n_slot + tb.noff[blk] + (size_t)k * rows * aV;
-  __bf16 *dst = Ns + (size_t)blockIdx.y * ns_slot + tb.noffs[blk] + (size_t)k * 2 * aV * JP;
-  for (int e = threadIdx.x; e < rows * aV; e += blockDim.x) sl[e] = src[e];
-  __syncthreads();
   const int units = 2 * aV * NO;
-  for (int u = threadIdx.x; u < units; u += blockDim.x) {
-    const int o = u % NO, pn = u / NO;
-    const int nu = pn % aV, part = pn / aV;
-    bf8 v;
+  const float *src = N + (size_t)blockIdx.y * n_slot + tb.noff[blk];
+  __bf16 *dst = Ns + (size_t)blockIdx.y * ns_slot + tb.noffs[blk];
+  for (int k = 0; k < nK; ++k, src += (size_t)rows * aV, dst += (size_t)2 * aV * JP) {
+    for (int e = threadIdx.x; e < rows * aV; e += blockDim.x) sl[e] = src[e];
+    __syncthreads();
+    for (int u = threadIdx.x; u < units; u += blockDim.x) {
+      const int o = u % NO, pn = u / NO;
+      const int nu = pn % aV, part = pn / aV;
+      bf8 v;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int jp = 8 * o + e;
-      const float xv = jp < rows ? sl[jp * aV + nu] : 0.f;
-      __bf16 h, l;
-      split_bf16(xv, h, l);
-      v[e] = part ? l : h;
+      for (int e = 0; e < 8; ++e) {
+        const int jp = 8 * o + e;
+        const float xv = jp < rows ? sl[jp * aV + nu] : 0.f;
+        __bf16 h, l;
+        split_bf16(xv, h, l);
+        v[e] = part ? l : h;
+      }
+      *reinterpret_cast<bf8 *>(dst + (size_t)pn * JP + 8 * o) = v;
     }
-    *reinterpret_cast<bf8 *>(dst + (size_t)pn * JP + 8 * o) = v;
+    __syncthreads();
   }
 }
 
 }  // namespace
 
-hipError_t launch_split_n(const Chi0Tables &tb, const long long *slices_start, long long nslices, const float *N,
-                          uint16_t *Ns, int nslots, size_t n_slot, size_t ns_slot, hipStream_t s) {
+hipError_t launch_split_n(const Chi0Tables &tb, const float *N, uint16_t *Ns, int nslots, size_t n_slot,
+                          size_t ns_slot, hipStream_t s) {
   const long long nblk = (long long)tb.natoms * tb.natoms * tb.nR;
-  if (nblk == 0 || nslices == 0 || nslots <= 0) return hipSuccess;
-  if (nslices > 0x7fffffffLL || nblk > 0x7fffffffLL) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(split_n_kernel, dim3((unsigned)nslices, nslots), dim3(256), 0, s, tb, slices_start, (int)nblk, N,
+  if (nblk == 0 || nslots <= 0) return hipSuccess;
+  if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(split_n_kernel, dim3((unsigned)nblk, nslots), dim3(256), 0, s, tb, N,
                      reinterpret_cast<__bf16 *>(Ns), n_slot, ns_slot);
   return hipGetLastError();
 }

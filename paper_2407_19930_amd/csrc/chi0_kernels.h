@@ -115,11 +115,10 @@ hipError_t launch_fused_bf16(const Chi0Tables &tb, const PairItems &items, int m
                              const uint16_t *Cb, const float *Nbuf, const uint16_t *Ns, double negs, const int *gexp,
                              const Screen &sc, double *chi, hipStream_t s);
 // Split-BF16 copy Ns (noffs layout, hi and lo parts) of the FP32 N intermediate of nslots tau
-// points (slot t at N + t n_slot and Ns + t ns_slot, elements); one workgroup per K(R1) slice of
-// every block, slices_start[b] = slices of the blocks before block b (device, natoms^2 nR),
-// nslices their total.
-hipError_t launch_split_n(const Chi0Tables &tb, const long long *slices_start, long long nslices, const float *N,
-                          uint16_t *Ns, int nslots, size_t n_slot, size_t ns_slot, hipStream_t s);
+// points (slot t at N + t n_slot and Ns + t ns_slot, elements); one workgroup per block (V, K,
+// dR) and slot, over the block's K(R1) slices.
+hipError_t launch_split_n(const Chi0Tables &tb, const float *N, uint16_t *Ns, int nslots, size_t n_slot,
+                          size_t ns_slot, hipStream_t s);
 
 // Single split-BF16 fused launch over the items of nslots tau points, every template class in one
 // launch (chi0_bf16.hip).  Per slot (tau of the launch): Gp, N, the two G-scale exponents, chi,
